@@ -1,0 +1,250 @@
+"""Time-to-tolerance benchmark: hierarchical vs global-memory Jacobi on the
+2D 5-point Poisson problem, 4096 x 4096 interior points, FP64, to relative
+residual 1e-6, on one MI355X.
+
+One step = solving the five seeded right-hand sides (8 random separable sine
+modes each, seeds 0-4) from x0 = 0, one after another, with inputs already
+resident in HBM.  `value` is the mean time to tolerance per problem.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--s 16] [--tile 32 32]
+                    [--overlap 0 0] [--seeds 0 1 2 3 4] [--no-cpu] [--no-global]
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_2006_16465_amd", "csrc", "hj_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cycle_bytes_per_launch(n, tile, overlap, esize=8):
+    """Algorithmic HBM bytes of one hierarchical cycle launch: every tile reads
+    its interior plus the edge halo ((tx+2)(ty+2) - 4 points of x), the f
+    values of its interior, and writes its owned points of x."""
+    from paper_2006_16465_amd import hj
+    tx, ty = tile
+    ntx = hj.axis_tiles(n, tx, overlap[0])
+    nty = hj.axis_tiles(n, ty, overlap[1])
+    ex, ey = min(tx, n), min(ty, n)
+    per_tile = ((ex + 2) * (ey + 2) - 4) + ex * ey
+    return esize * (ntx * nty * per_tile + n * n)
+
+
+def sweep_bytes_per_launch(n, esize=8):
+    """Algorithmic HBM bytes of one global sweep: read x and f, write x."""
+    return 3 * esize * n * n
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def load_traffic(name):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(PROFILES, f"{name}.counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--tile", type=int, nargs=2, default=[32, 32])
+    ap.add_argument("--s", type=int, default=16)
+    ap.add_argument("--overlap", type=int, nargs=2, default=[0, 0])
+    ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1, 2, 3, 4])
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--check-every", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-global", action="store_true", help="skip the global-memory baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample budget")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the method runs on a single device); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2006_16465_amd import hj
+    from paper_2006_16465_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    hj.load()
+    dev = torch.device("cuda:0")
+    n = args.n
+    h = W.grid_h(n)
+    tile, ov, s = tuple(args.tile), tuple(args.overlap), args.s
+
+    log(f"generating {len(args.seeds)} right-hand sides {n}x{n} ...")
+    fs = [torch.from_numpy(W.rhs_2d_modes(n, n, 8, 0.0, sd)).to(dev) for sd in args.seeds]
+    xs = [torch.zeros_like(fs[0]) for _ in fs]
+    stream = torch.cuda.current_stream(dev)
+
+    def run_all(method):
+        """Solve every seed once; returns per-seed (ms by events, info)."""
+        out = []
+        for f, x in zip(fs, xs):
+            x.zero_()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            info = hj.solve_2d(f, x, h, tile=tile, s=s, overlap=ov, method=method,
+                               rel_tol=args.tol, check_every=args.check_every)
+            e1.record(stream)
+            e1.synchronize()
+            out.append((e0.elapsed_time(e1), info))
+        return out
+
+    def timed(method, steps, warmup):
+        for _ in range(warmup):
+            run_all(method)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        per = [run_all(method) for _ in range(steps)]
+        torch.cuda.synchronize()
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        return wall_ms, per
+
+    log(f"hierarchical: tile={tile} s={s} overlap={ov}, {args.warmup} warmup + {args.steps} steps")
+    wall_h, per_h = timed("hierarchical", args.steps, args.warmup)
+    ms_per_step = wall_h / args.steps
+    nprob = len(fs)
+    cycles_h = [info.cycles for _, info in per_h[0]]
+    ev_ms_h = np.array([[ms for ms, _ in step] for step in per_h])  # steps x seeds
+    seed_ms_h = np.median(ev_ms_h, axis=0)
+
+    # dominant kernel: the hierarchical cycle with fused residual; each solve
+    # launches it cycles + 1 times with real work (the last computes the
+    # residual that stops the loop)
+    bpl = cycle_bytes_per_launch(n, tile, ov)
+    launches = sum(c + 1 for c in cycles_h)
+    avg_launch_s = float(ev_ms_h.sum(axis=1).mean()) * 1e-3 / launches
+    achieved = bpl / avg_launch_s / 1e9
+    kname = f"cycle2d_f64_t{tile[0]}x{tile[1]}_s{s}_o{ov[0]}x{ov[1]}_n{n}"
+    traffic = load_traffic(kname)
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": f"k_cycle2d<double,{tile[0]},{tile[1]},res,iso>",
+        "algorithmic_bytes_per_launch": bpl,
+        "avg_launch_us": round(avg_launch_s * 1e6, 2),
+        "launches_per_step": launches,
+    }
+
+    extra = {
+        "cycles_per_seed": dict(zip(map(str, args.seeds), cycles_h)),
+        "ms_per_seed": dict(zip(map(str, args.seeds), [round(float(v), 3) for v in seed_ms_h])),
+        "rel_residual_per_seed": [info.rel_residual for _, info in per_h[0]],
+    }
+
+    glob = None
+    if not args.no_global:
+        log("global-memory Jacobi baseline")
+        wall_g, per_g = timed("global", max(1, args.steps), args.warmup)
+        ev_ms_g = np.array([[ms for ms, _ in step] for step in per_g])
+        sweeps_g = [info.cycles for _, info in per_g[0]]
+        seed_ms_g = np.median(ev_ms_g, axis=0)
+        glaunch = sum(c + 1 for c in sweeps_g)
+        g_avg = float(ev_ms_g.sum(axis=1).mean()) * 1e-3 / glaunch
+        glob = {
+            "ms_per_problem": round(wall_g / max(1, args.steps) / nprob, 3),
+            "sweeps_per_seed": dict(zip(map(str, args.seeds), sweeps_g)),
+            "ms_per_seed": dict(zip(map(str, args.seeds), [round(float(v), 3) for v in seed_ms_g])),
+            "sweep_kernel_gbs": round(sweep_bytes_per_launch(n) / g_avg / 1e9, 1),
+            "avg_launch_us": round(g_avg * 1e6, 2),
+        }
+        extra["global_baseline"] = glob
+        extra["speedup_vs_global"] = round(glob["ms_per_problem"] / (ms_per_step / nprob), 3)
+        extra["speedup_vs_global_per_seed"] = {
+            k: round(glob["ms_per_seed"][k] / extra["ms_per_seed"][k], 3) for k in glob["ms_per_seed"]}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args, W, cycles_h, tile, ov, s)
+
+    line = {
+        "metric": "time to rel. residual 1e-6 (2D 4096^2) + achieved HBM GB/s, hierarchical vs global Jacobi",
+        "value": round(ms_per_step / nprob, 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"poisson2d_{n}: 2D 5-point Poisson {n}x{n}, Dirichlet 0, f = 8 random separable "
+                        f"sine modes (seeds {args.seeds}), x0 = 0, to rel. residual {args.tol:g}; one step "
+                        f"= all seeds solved once; value = mean ms per problem",
+            "n": n, "tile": list(tile), "s": s, "overlap": list(ov), "tol": args.tol,
+            "seeds": args.seeds, "method": "hierarchical", "check_every": args.check_every,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        **extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(args, W, cycles_h, tile, ov, s):
+    """The CPU oracle, as it stands, on a bounded sample: a few cycles of the
+    same hierarchical solve (residual checked every cycle), timed per cycle and
+    scaled to the cycle counts of the full solves."""
+    import oracle
+    n = args.n
+    h = W.grid_h(n)
+    sd = args.seeds[0]
+    f = W.rhs_2d_modes(n, n, 8, 0.0, sd)
+    x0 = np.zeros_like(f)
+    oracle._load()
+    log("cpu baseline: timing the oracle ...")
+    t0 = time.perf_counter()
+    oracle.solve_2d(f, x0, h, h, tile=tile, s=s, tol=args.tol, max_cycles=1, overlap=ov)
+    one = time.perf_counter() - t0
+    k = int(max(2, min(200, args.cpu_seconds / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    _, c, _, _ = oracle.solve_2d(f, x0, h, h, tile=tile, s=s, tol=args.tol, max_cycles=k, overlap=ov)
+    el = time.perf_counter() - t0
+    ran = k if c < 0 else c
+    per_cycle = el / max(ran, 1)
+    est_ms = per_cycle * float(np.mean(cycles_h)) * 1e3
+    return {
+        "value": round(est_ms, 1), "unit": "ms", "cores": oracle.num_threads(), "kind": "oracle",
+        "sample": f"{ran} hierarchical cycles (residual each cycle) of the {n}x{n} seed-{sd} solve, "
+                  f"{el:.1f} s, scaled to the mean GPU cycle count {float(np.mean(cycles_h)):.1f}",
+    }
+
+
+if __name__ == "__main__":
+    main()

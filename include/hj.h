@@ -1,0 +1,158 @@
+/*
+ * hj.h -- C ABI of the MI355X (gfx950) hierarchical Jacobi library (libhj.so).
+ *
+ * Method: Islam & Wang, "Hierarchical Jacobi Iteration for Structured Matrices
+ * on GPUs using Shared Memory" (arXiv:2006.16465).
+ *
+ * Problems solved (Sec. 3.4 and Sec. 4.2): the finite-difference Poisson
+ * systems A x = f with homogeneous Dirichlet boundaries,
+ *   1D:  -u'' = f on [0,1], A = tridiag(-1, 2, -1) / h^2, n interior points;
+ *   2D:  -(u_xx + u_yy) = f on [0,1]^2, 5-point stencil with weights
+ *        1/hx^2 (x neighbours) and 1/hy^2 (y neighbours), diagonal
+ *        2/hx^2 + 2/hy^2, nx * ny interior points.
+ *
+ * Iterations:
+ *   HJ_GLOBAL       classical Jacobi (Sec. 2.1 elemental update, Sec. 3.2 / 4.2
+ *                   global-memory GPU version): one sweep of the whole grid per
+ *                   cycle.
+ *   HJ_HIERARCHICAL the hierarchical cycle (Sec. 3.3 three steps; Sec. 4.1 in
+ *                   2D): each tile plus a one-point halo is copied on chip, s
+ *                   Jacobi sub-iterations run on the tile interior with the halo
+ *                   frozen at the previous global iterate, and the interior is
+ *                   written to a second global array.  With overlap o > 0
+ *                   (Sec. 3.5 / 4.3) neighbouring tiles share o interior points
+ *                   and each shared point is written by the tile in which it is
+ *                   farther from the frozen edge.  s = 1 reproduces classical
+ *                   Jacobi iterates exactly.
+ *
+ * Tile partition of an axis of n points (tile t, overlap o, 0 <= o < t): if
+ * n <= t, one tile covers all points; otherwise ceil((n - o) / (t - o)) full
+ * tiles at stride t - o, the last moved left so that it ends at point n.  Where
+ * two neighbours overlap in [a, b) the left tile writes the first
+ * ceil((b - a) / 2) points.  The 2D partition is the product of the per-axis
+ * partitions.
+ *
+ * Arithmetic (IEEE round-to-nearest, no fused multiply-add, no flush to zero):
+ *   1D:          x_i <- (h^2 f_i + (x_{i-1} + x_{i+1})) * 0.5
+ *   2D, hx==hy:  x   <- (h^2 f + ((x_W + x_E) + (x_S + x_N))) * 0.25
+ *   2D, hx!=hy:  x   <- (f + (wx (x_W + x_E) + wy (x_S + x_N))) * dinv
+ * with h^2 f rounded once, wx = 1/hx^2, wy = 1/hy^2, dinv = 1/(2 wx + 2 wy),
+ * W/E the x neighbours (same row), S/N the y neighbours (adjacent rows).  In
+ * FP64 the iterates are therefore bit-reproducible and independent of the
+ * order in which tiles run.
+ *
+ * Residual: r = f - A x over the interior, its 2-norm accumulated in FP64 with
+ * a fixed-order reduction (deterministic run to run).  A solve stops at the
+ * first cycle c with ||r_c||_2 <= rel_tol * ||r_0||_2 (the paper's stopping
+ * rule, Sec. 3.4, with the factor 1e-4 replaced by rel_tol); the residual is
+ * evaluated for every cycle on the global iterate, fused into the next
+ * cycle's tile load.
+ *
+ * Memory layout: all arrays are device memory of the selected dtype.  1D
+ * arrays hold the n interior points contiguously.  2D arrays are row-major
+ * with leading dimension ld >= nx elements: point (row y = j, column x = i) is
+ * at [j * ld + i]; f, x and r_out share ld.  Columns nx..ld-1 are never read
+ * or written.  Pointers must be aligned to the element size.
+ *
+ * Ownership: the caller owns f, x and r_out.  The library owns its scratch
+ * (one second iterate array of the same size as x, and a few KB of reduction
+ * partials and control words), allocated on first use per device and size and
+ * kept until the process ends.  Calls are synchronous with respect to the
+ * stream passed in: they enqueue work on it and return after it has drained.
+ * Calls from several host threads on one device are serialised internally.
+ *
+ * Errors: every entry point validates its arguments before any HIP call and
+ * returns a status; no C++ exception crosses the ABI.  hj_last_error() gives a
+ * detail string for the last failing call of the calling thread.
+ */
+#ifndef HJ_H
+#define HJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hj_status {
+    HJ_OK = 0,
+    HJ_ERR_INVALID_ARG = 1,   /* argument validation failed; nothing was run */
+    HJ_ERR_NOT_CONVERGED = 2, /* max_cycles reached; x and info hold the last iterate */
+    HJ_ERR_NONFINITE = 3,     /* a residual norm became NaN/Inf; x holds that iterate */
+    HJ_ERR_UNSUPPORTED = 4,   /* valid but not provided (tile shape, entry point) */
+    HJ_ERR_HIP = 5            /* a HIP runtime call failed; see hj_last_error() */
+} hj_status;
+
+typedef enum hj_dtype { HJ_F64 = 0, HJ_F32 = 1 } hj_dtype;
+
+typedef enum hj_method { HJ_HIERARCHICAL = 0, HJ_GLOBAL = 1 } hj_method;
+
+typedef struct hj_params {
+    int32_t tile_x;      /* interior tile extent along x (1D: the tile); 0 = 32.
+                            2D supports 16, 32, 64; 1D supports 32..1024 (powers of 2) */
+    int32_t tile_y;      /* interior tile extent along y (2D); 0 = 32 */
+    int32_t overlap_x;   /* interior points shared by x-neighbour tiles, 0 <= o < tile */
+    int32_t overlap_y;   /* same along y */
+    int32_t s;           /* sub-iterations per cycle (the paper's k), >= 1; ignored by HJ_GLOBAL */
+    int32_t method;      /* hj_method */
+    int64_t max_cycles;  /* >= 1: cycles (HJ_GLOBAL: sweeps) allowed */
+    int32_t check_every; /* cycles enqueued between host polls of the device-side
+                            convergence flag; 0 = 32.  Does not change results. */
+    int32_t flags;       /* must be 0 */
+    double rel_tol;      /* > 0: stop at the first cycle c with ||r_c|| <= rel_tol ||r_0||.
+                            <= 0: run exactly max_cycles cycles with no residual
+                            evaluation in between (fixed-count mode). */
+} hj_params;
+
+typedef struct hj_info {
+    int64_t cycles;      /* index c of the iterate returned in x */
+    int64_t sweeps;      /* Jacobi sweeps applied per point: cycles * s (HIERARCHICAL) or cycles */
+    double rel_residual; /* ||f - A x_c|| / ||f - A x_0|| (0 if ||f - A x_0|| == 0) */
+    double r0_norm;      /* ||f - A x_0||_2 */
+} hj_info;
+
+/* Fill *p with defaults: 32 (x 32) tiles, no overlap, s = 16, hierarchical,
+ * max_cycles = 1000000, check_every = 32, rel_tol = 1e-6. */
+void hj_params_default(hj_params *p);
+
+/* 1D solve (Sec. 3).  n >= 1 interior points, spacing h > 0.  f: n values,
+ * x: n values, in/out (x_0 in, x_cycles out).  stream: hipStream_t or NULL for
+ * the null stream.  info may be NULL.  Returns HJ_OK on convergence (or after
+ * max_cycles in fixed-count mode). */
+hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *x,
+                      const hj_params *p, void *stream, hj_info *info);
+
+/* 2D solve (Sec. 4).  nx, ny >= 1, ld >= nx, hx, hy > 0; f and x: ny rows of
+ * ld elements; x in/out. */
+hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
+                      const void *f, void *x, const hj_params *p, void *stream, hj_info *info);
+
+/* Residual r = f - A x (Sec. 3.4 / 4.2 operator) and ||r||_2 (FP64).
+ * dim = 1 (uses nx = n, ny and ld ignored, hx = h) or 2.  r_out (same dtype and
+ * layout as x) may be NULL; norm2_out (host) may be NULL. */
+hj_status hj_residual(int32_t dim, int64_t nx, int64_t ny, int64_t ld, double hx, double hy,
+                      hj_dtype dtype, const void *f, const void *x, void *r_out,
+                      double *norm2_out, void *stream);
+
+/* Many independent problems in one launch.  Declared for a later version;
+ * returns HJ_ERR_UNSUPPORTED. */
+hj_status hj_solve_batched(const void *desc, int64_t nprob, const hj_params *p, void *stream,
+                           void *infos);
+
+/* Adjoint solve for the variable-coefficient operator.  Declared for a later
+ * version; returns HJ_ERR_UNSUPPORTED. */
+hj_status hj_solve_adjoint(const void *desc, void *stream, void *info);
+
+/* Number of tiles (workgroups of the cycle kernel) along one axis; the same
+ * partition rule the kernels use.  Returns -1 on invalid arguments. */
+int64_t hj_axis_tiles(int64_t n, int32_t tile, int32_t overlap);
+
+const char *hj_status_string(hj_status s);
+const char *hj_last_error(void);   /* thread-local; "" if none */
+const char *hj_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HJ_H */

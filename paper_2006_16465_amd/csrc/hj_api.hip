@@ -1,0 +1,446 @@
+// hj_api.hip -- C ABI of libhj: argument validation, per-device scratch, and
+// the host loop that enqueues cycles and polls the device-side convergence
+// flag (declarations and contracts in include/hj.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <mutex>
+#include <string>
+
+#include "hj.h"
+#include "hj_launch.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+hj_status fail(hj_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+hj_status hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return HJ_ERR_HIP;
+}
+
+#define HJ_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------- scratch
+// One set per device: a second iterate array, reduction partials, the control
+// block and two pinned host slots for polling it.  Grown on demand, kept until
+// the process ends.  The mutex serialises calls on one device.
+struct DevScratch {
+    std::mutex mu;
+    bool ready = false;
+    void *xbuf = nullptr;
+    size_t xbytes = 0;
+    double *partials = nullptr;
+    int64_t npart = 0;
+    hj::Ctrl *ctrl = nullptr;
+    hj::Ctrl *host = nullptr;  // 2 pinned slots
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+constexpr int kMaxDev = 64;
+DevScratch g_scr[kMaxDev];
+
+hj_status scratch_ensure(DevScratch &S, size_t xbytes, int64_t npart)
+{
+    if (!S.ready) {
+        HJ_HIP(hipMalloc((void **)&S.ctrl, sizeof(hj::Ctrl)));
+        HJ_HIP(hipHostMalloc((void **)&S.host, 2 * sizeof(hj::Ctrl), hipHostMallocDefault));
+        HJ_HIP(hipEventCreateWithFlags(&S.ev[0], hipEventDisableTiming));
+        HJ_HIP(hipEventCreateWithFlags(&S.ev[1], hipEventDisableTiming));
+        S.ready = true;
+    }
+    if (xbytes > S.xbytes) {
+        if (S.xbuf) HJ_HIP(hipFree(S.xbuf));
+        S.xbuf = nullptr;
+        S.xbytes = 0;
+        HJ_HIP(hipMalloc(&S.xbuf, xbytes));
+        S.xbytes = xbytes;
+    }
+    if (npart > S.npart) {
+        if (S.partials) HJ_HIP(hipFree(S.partials));
+        S.partials = nullptr;
+        S.npart = 0;
+        HJ_HIP(hipMalloc((void **)&S.partials, (size_t)npart * sizeof(double)));
+        S.npart = npart;
+    }
+    return HJ_OK;
+}
+
+// ---------------------------------------------------------------- validation
+size_t esize(hj_dtype dt) { return dt == HJ_F64 ? 8 : 4; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+hj_status check_ptr_dtype(const void *p, hj_dtype dt, const char *name, bool may_be_null)
+{
+    if (!p) return may_be_null ? HJ_OK : fail(HJ_ERR_INVALID_ARG, std::string(name) + " is NULL");
+    if ((uintptr_t)p % esize(dt))
+        return fail(HJ_ERR_INVALID_ARG, std::string(name) + " is not aligned to the element size");
+    return HJ_OK;
+}
+
+hj_status check_params(const hj_params *p, int dim)
+{
+    if (!p) return fail(HJ_ERR_INVALID_ARG, "params is NULL");
+    if (p->flags != 0) return fail(HJ_ERR_INVALID_ARG, "params.flags must be 0");
+    if (p->method != HJ_HIERARCHICAL && p->method != HJ_GLOBAL)
+        return fail(HJ_ERR_INVALID_ARG, "params.method must be HJ_HIERARCHICAL or HJ_GLOBAL");
+    if (p->max_cycles < 1) return fail(HJ_ERR_INVALID_ARG, "params.max_cycles must be >= 1");
+    if (p->check_every < 0) return fail(HJ_ERR_INVALID_ARG, "params.check_every must be >= 0");
+    if (std::isnan(p->rel_tol)) return fail(HJ_ERR_INVALID_ARG, "params.rel_tol is NaN");
+    if (p->method == HJ_HIERARCHICAL) {
+        if (p->s < 1) return fail(HJ_ERR_INVALID_ARG, "params.s must be >= 1");
+        const int tx = p->tile_x ? p->tile_x : 32;
+        const int ty = p->tile_y ? p->tile_y : 32;
+        if (tx < 1 || (dim == 2 && ty < 1)) return fail(HJ_ERR_INVALID_ARG, "tile extents must be >= 1");
+        if (p->overlap_x < 0 || p->overlap_x >= tx)
+            return fail(HJ_ERR_INVALID_ARG, "params.overlap_x must satisfy 0 <= overlap_x < tile_x");
+        if (dim == 2 && (p->overlap_y < 0 || p->overlap_y >= ty))
+            return fail(HJ_ERR_INVALID_ARG, "params.overlap_y must satisfy 0 <= overlap_y < tile_y");
+        if (dim == 2 && !hj::cycle2d_supported(tx, ty))
+            return fail(HJ_ERR_UNSUPPORTED, "2D tile shape not provided (tile_x, tile_y in {16, 32, 64})");
+        if (dim == 1 && !hj::cycle1d_supported(tx))
+            return fail(HJ_ERR_UNSUPPORTED, "1D tile not provided (32, 64, ..., 1024)");
+    }
+    return HJ_OK;
+}
+
+// Device pointers must live on the current device (a host pointer handed to a
+// kernel would fault).
+hj_status check_device_ptr(const void *p, int dev, const char *name)
+{
+    if (!p) return HJ_OK;
+    hipPointerAttribute_t a;
+    std::memset(&a, 0, sizeof(a));
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HJ_ERR_INVALID_ARG, std::string(name) + " is not device memory");
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+        return fail(HJ_ERR_INVALID_ARG, std::string(name) + " is not device memory");
+    if (a.device != dev)
+        return fail(HJ_ERR_INVALID_ARG, std::string(name) + " lives on another device");
+    return HJ_OK;
+}
+
+// ---------------------------------------------------------------- driver
+struct Step {
+    // one cycle reading xin writing xout; res = fused residual of xin
+    std::function<hipError_t(const void *, void *, bool, double)> cycle;
+    // residual of x judged as iterate c
+    std::function<hipError_t(const void *, int64_t, double)> resid;
+    // copy scratch -> user x
+    std::function<hipError_t(void *, const void *)> copy;
+};
+
+hj_status drive(const Step &st, void *xu, void *xs, const hj_params &p, int64_t spc,
+                hipStream_t stream, DevScratch &S, hj_info *info)
+{
+    void *bufs[2] = {xu, xs};
+    const int64_t maxc = p.max_cycles;
+    const int batch = p.check_every > 0 ? p.check_every : 32;
+    HJ_HIP(hj::launch_ctrl_init(S.ctrl, stream));
+    int64_t final_c = maxc;
+    hj::Ctrl c{};
+    if (p.rel_tol <= 0.0) {
+        HJ_HIP(st.resid(bufs[0], 0, -1.0));
+        for (int64_t k = 0; k < maxc; ++k) HJ_HIP(st.cycle(bufs[k & 1], bufs[(k + 1) & 1], false, -1.0));
+        HJ_HIP(st.resid(bufs[maxc & 1], maxc, -1.0));
+        HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
+        HJ_HIP(hipStreamSynchronize(stream));
+        c = S.host[0];
+    } else {
+        const double tol = p.rel_tol;
+        int64_t next = 0;
+        auto enqueue = [&](int slot) -> hj_status {
+            const int64_t k = std::min<int64_t>(batch, maxc - next);
+            for (int64_t i = 0; i < k; ++i) {
+                const int64_t cc = next + i;
+                HJ_HIP(st.cycle(bufs[cc & 1], bufs[(cc + 1) & 1], true, tol));
+            }
+            next += k;
+            HJ_HIP(hipMemcpyAsync(&S.host[slot], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
+            HJ_HIP(hipEventRecord(S.ev[slot], stream));
+            return HJ_OK;
+        };
+        hj_status r = enqueue(0);
+        if (r != HJ_OK) return r;
+        int slot = 0;
+        for (;;) {
+            const bool more = next < maxc;
+            if (more) {
+                r = enqueue(slot ^ 1);  // keep the GPU fed while this batch is checked
+                if (r != HJ_OK) return r;
+            }
+            HJ_HIP(hipEventSynchronize(S.ev[slot]));
+            if (S.host[slot].status != hj::ST_RUNNING || !more) break;
+            slot ^= 1;
+        }
+        HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
+        HJ_HIP(hipStreamSynchronize(stream));
+        c = S.host[0];
+        if (c.status == hj::ST_RUNNING) {
+            // all max_cycles cycles ran; judge the last iterate too
+            HJ_HIP(st.resid(bufs[maxc & 1], maxc, tol));
+            HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
+            HJ_HIP(hipStreamSynchronize(stream));
+            c = S.host[0];
+        }
+        final_c = c.status != hj::ST_RUNNING ? c.done_cycle : maxc;
+    }
+    if (final_c & 1) {
+        HJ_HIP(st.copy(xu, xs));
+        HJ_HIP(hipStreamSynchronize(stream));
+    }
+    if (info) {
+        info->cycles = final_c;
+        info->sweeps = final_c * spc;
+        info->r0_norm = std::sqrt(c.r0sq);
+        info->rel_residual = c.r0sq > 0.0 ? std::sqrt(c.last_rsq) / std::sqrt(c.r0sq) : 0.0;
+        if (!std::isfinite(c.last_rsq)) info->rel_residual = NAN;
+    }
+    if (c.status == hj::ST_NONFINITE) return fail(HJ_ERR_NONFINITE, "residual norm became non-finite");
+    if (p.rel_tol > 0.0 && c.status != hj::ST_CONVERGED)
+        return fail(HJ_ERR_NOT_CONVERGED, "max_cycles reached before rel_tol");
+    return HJ_OK;
+}
+
+hj::Geom2 make_geom2(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, const hj_params &p)
+{
+    hj::Geom2 g;
+    g.nx = (int)nx;
+    g.ny = (int)ny;
+    g.ld = ld;
+    g.tx = p.tile_x ? p.tile_x : 32;
+    g.ty = p.tile_y ? p.tile_y : 32;
+    g.ox = p.overlap_x;
+    g.oy = p.overlap_y;
+    g.ntx = hj::axis_count(g.nx, g.tx, g.ox);
+    g.nty = hj::axis_count(g.ny, g.ty, g.oy);
+    g.iso = hx == hy;
+    g.hh = hx * hx;
+    g.wx = 1.0 / (hx * hx);
+    g.wy = 1.0 / (hy * hy);
+    g.dinv = 1.0 / (2.0 * g.wx + 2.0 * g.wy);
+    return g;
+}
+
+hj::Geom1 make_geom1(int64_t n, double h, const hj_params *p)
+{
+    hj::Geom1 g;
+    g.n = n;
+    g.t = p && p->tile_x ? p->tile_x : 32;
+    g.o = p ? p->overlap_x : 0;
+    g.nt = hj::axis_count((int)n, g.t, g.o);
+    g.hh = h * h;
+    g.w1 = 1.0 / (h * h);
+    return g;
+}
+
+constexpr int64_t kMaxAxis = (int64_t)1 << 30;
+
+}  // namespace
+
+extern "C" {
+
+void hj_params_default(hj_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->tile_x = 32;
+    p->tile_y = 32;
+    p->s = 16;
+    p->method = HJ_HIERARCHICAL;
+    p->max_cycles = 1000000;
+    p->check_every = 32;
+    p->rel_tol = 1e-6;
+}
+
+hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
+                      const void *f, void *x, const hj_params *p, void *stream, hj_info *info)
+{
+    g_err.clear();
+    if (nx < 1 || ny < 1 || nx > kMaxAxis || ny > kMaxAxis)
+        return fail(HJ_ERR_INVALID_ARG, "nx, ny must be in [1, 2^30]");
+    if (ld < nx) return fail(HJ_ERR_INVALID_ARG, "ld must be >= nx");
+    if (!finite_pos(hx) || !finite_pos(hy)) return fail(HJ_ERR_INVALID_ARG, "hx, hy must be finite and > 0");
+    if (dtype != HJ_F64 && dtype != HJ_F32) return fail(HJ_ERR_INVALID_ARG, "unknown dtype");
+    hj_status r;
+    if ((r = check_ptr_dtype(f, dtype, "f", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(x, dtype, "x", false)) != HJ_OK) return r;
+    if ((r = check_params(p, 2)) != HJ_OK) return r;
+
+    int dev = 0;
+    HJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
+    if ((r = check_device_ptr(f, dev, "f")) != HJ_OK) return r;
+    if ((r = check_device_ptr(x, dev, "x")) != HJ_OK) return r;
+
+    DevScratch &S = g_scr[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    const hj_params P = *p;
+    const hj::Geom2 g = make_geom2(nx, ny, ld, hx, hy, P);
+    const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
+    const size_t es = esize(dtype);
+    const bool hier = P.method == HJ_HIERARCHICAL;
+    int64_t npart = hj::resid2d_blocks(g);
+    npart = std::max(npart, hier ? hj::cycle2d_blocks(g) : hj::sweep2d_blocks(g));
+    if ((r = scratch_ensure(S, (size_t)ny * (size_t)ld * es, npart)) != HJ_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+
+    Step step;
+    step.cycle = [&](const void *xi, void *xo, bool res, double tol) {
+        return hier ? hj::launch_cycle2d(dt, g, P.s, res, f, xi, xo, S.partials, S.ctrl, tol, st)
+                    : hj::launch_sweep2d(dt, g, res, f, xi, xo, S.partials, S.ctrl, tol, st);
+    };
+    step.resid = [&](const void *xi, int64_t c, double tol) {
+        return hj::launch_resid2d(dt, g, f, xi, nullptr, S.partials, S.ctrl, c, tol, st);
+    };
+    step.copy = [&](void *dst, const void *src) {
+        return hipMemcpy2DAsync(dst, (size_t)ld * es, src, (size_t)ld * es, (size_t)nx * es,
+                                (size_t)ny, hipMemcpyDeviceToDevice, st);
+    };
+    return drive(step, x, S.xbuf, P, hier ? P.s : 1, st, S, info);
+}
+
+hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *x,
+                      const hj_params *p, void *stream, hj_info *info)
+{
+    g_err.clear();
+    if (n < 1 || n > kMaxAxis) return fail(HJ_ERR_INVALID_ARG, "n must be in [1, 2^30]");
+    if (!finite_pos(h)) return fail(HJ_ERR_INVALID_ARG, "h must be finite and > 0");
+    if (dtype != HJ_F64 && dtype != HJ_F32) return fail(HJ_ERR_INVALID_ARG, "unknown dtype");
+    hj_status r;
+    if ((r = check_ptr_dtype(f, dtype, "f", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(x, dtype, "x", false)) != HJ_OK) return r;
+    if ((r = check_params(p, 1)) != HJ_OK) return r;
+
+    int dev = 0;
+    HJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
+    if ((r = check_device_ptr(f, dev, "f")) != HJ_OK) return r;
+    if ((r = check_device_ptr(x, dev, "x")) != HJ_OK) return r;
+
+    DevScratch &S = g_scr[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    const hj_params P = *p;
+    const hj::Geom1 g = make_geom1(n, h, &P);
+    const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
+    const size_t es = esize(dtype);
+    const bool hier = P.method == HJ_HIERARCHICAL;
+    int64_t npart = hj::resid1d_blocks(g);
+    npart = std::max(npart, hier ? hj::cycle1d_blocks(g) : hj::sweep1d_blocks(g));
+    if ((r = scratch_ensure(S, (size_t)n * es, npart)) != HJ_OK) return r;
+    hipStream_t st = (hipStream_t)stream;
+
+    Step step;
+    step.cycle = [&](const void *xi, void *xo, bool res, double tol) {
+        return hier ? hj::launch_cycle1d(dt, g, P.s, res, f, xi, xo, S.partials, S.ctrl, tol, st)
+                    : hj::launch_sweep1d(dt, g, res, f, xi, xo, S.partials, S.ctrl, tol, st);
+    };
+    step.resid = [&](const void *xi, int64_t c, double tol) {
+        return hj::launch_resid1d(dt, g, f, xi, nullptr, S.partials, S.ctrl, c, tol, st);
+    };
+    step.copy = [&](void *dst, const void *src) {
+        return hipMemcpyAsync(dst, src, (size_t)n * es, hipMemcpyDeviceToDevice, st);
+    };
+    return drive(step, x, S.xbuf, P, hier ? P.s : 1, st, S, info);
+}
+
+hj_status hj_residual(int32_t dim, int64_t nx, int64_t ny, int64_t ld, double hx, double hy,
+                      hj_dtype dtype, const void *f, const void *x, void *r_out, double *norm2_out,
+                      void *stream)
+{
+    g_err.clear();
+    if (dim != 1 && dim != 2) return fail(HJ_ERR_INVALID_ARG, "dim must be 1 or 2");
+    if (nx < 1 || nx > kMaxAxis) return fail(HJ_ERR_INVALID_ARG, "nx must be in [1, 2^30]");
+    if (dim == 2 && (ny < 1 || ny > kMaxAxis)) return fail(HJ_ERR_INVALID_ARG, "ny must be in [1, 2^30]");
+    if (dim == 2 && ld < nx) return fail(HJ_ERR_INVALID_ARG, "ld must be >= nx");
+    if (!finite_pos(hx) || (dim == 2 && !finite_pos(hy)))
+        return fail(HJ_ERR_INVALID_ARG, "spacings must be finite and > 0");
+    if (dtype != HJ_F64 && dtype != HJ_F32) return fail(HJ_ERR_INVALID_ARG, "unknown dtype");
+    hj_status r;
+    if ((r = check_ptr_dtype(f, dtype, "f", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(x, dtype, "x", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(r_out, dtype, "r_out", true)) != HJ_OK) return r;
+
+    int dev = 0;
+    HJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
+    if ((r = check_device_ptr(f, dev, "f")) != HJ_OK) return r;
+    if ((r = check_device_ptr(x, dev, "x")) != HJ_OK) return r;
+    if ((r = check_device_ptr(r_out, dev, "r_out")) != HJ_OK) return r;
+
+    DevScratch &S = g_scr[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
+    hipStream_t st = (hipStream_t)stream;
+    if (dim == 2) {
+        hj_params P;
+        hj_params_default(&P);
+        const hj::Geom2 g = make_geom2(nx, ny, ld, hx, hy, P);
+        if ((r = scratch_ensure(S, 0, hj::resid2d_blocks(g))) != HJ_OK) return r;
+        HJ_HIP(hj::launch_ctrl_init(S.ctrl, st));
+        HJ_HIP(hj::launch_resid2d(dt, g, f, x, r_out, S.partials, S.ctrl, 0, -1.0, st));
+    } else {
+        const hj::Geom1 g = make_geom1(nx, hx, nullptr);
+        if ((r = scratch_ensure(S, 0, hj::resid1d_blocks(g))) != HJ_OK) return r;
+        HJ_HIP(hj::launch_ctrl_init(S.ctrl, st));
+        HJ_HIP(hj::launch_resid1d(dt, g, f, x, r_out, S.partials, S.ctrl, 0, -1.0, st));
+    }
+    HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, st));
+    HJ_HIP(hipStreamSynchronize(st));
+    if (norm2_out) *norm2_out = std::sqrt(S.host[0].last_rsq);
+    if (!std::isfinite(S.host[0].last_rsq)) return fail(HJ_ERR_NONFINITE, "residual norm is non-finite");
+    return HJ_OK;
+}
+
+hj_status hj_solve_batched(const void *, int64_t, const hj_params *, void *, void *)
+{
+    return fail(HJ_ERR_UNSUPPORTED, "hj_solve_batched is not provided by this version");
+}
+
+hj_status hj_solve_adjoint(const void *, void *, void *)
+{
+    return fail(HJ_ERR_UNSUPPORTED, "hj_solve_adjoint is not provided by this version");
+}
+
+int64_t hj_axis_tiles(int64_t n, int32_t tile, int32_t overlap)
+{
+    if (n < 1 || n > kMaxAxis || tile < 1 || overlap < 0 || overlap >= tile) return -1;
+    return hj::axis_count((int)n, tile, overlap);
+}
+
+const char *hj_status_string(hj_status s)
+{
+    switch (s) {
+    case HJ_OK: return "HJ_OK";
+    case HJ_ERR_INVALID_ARG: return "HJ_ERR_INVALID_ARG";
+    case HJ_ERR_NOT_CONVERGED: return "HJ_ERR_NOT_CONVERGED";
+    case HJ_ERR_NONFINITE: return "HJ_ERR_NONFINITE";
+    case HJ_ERR_UNSUPPORTED: return "HJ_ERR_UNSUPPORTED";
+    case HJ_ERR_HIP: return "HJ_ERR_HIP";
+    }
+    return "HJ_ERR_UNKNOWN";
+}
+
+const char *hj_last_error(void) { return g_err.c_str(); }
+
+const char *hj_version(void) { return "hj 0.1 (gfx950)"; }
+
+}  // extern "C"

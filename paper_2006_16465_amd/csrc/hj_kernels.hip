@@ -1,0 +1,504 @@
+// hj_kernels.hip -- gfx950 kernels for hierarchical and classical Jacobi on the
+// 1D 3-point and 2D 5-point Poisson operators (Islam & Wang, arXiv:2006.16465).
+//
+// Cycle kernels implement the three steps of Sec. 3.3 (2D: Sec. 4.1): one
+// workgroup per tile copies the tile and its one-point halo from HBM into LDS,
+// runs s Jacobi sub-iterations on the interior with the halo frozen (two LDS
+// buffers, Sec. 3.3 even/odd containers), and writes its owned interior points
+// to a second global array.  The residual of the iterate being read is
+// computed from the same LDS tile at no extra HBM traffic and reduced
+// grid-wide in FP64.
+//
+// Build with -ffp-contract=off: the update association below is part of the
+// result and must not be fused.
+#include <hip/hip_runtime.h>
+
+#include "hj_launch.h"
+
+namespace hj {
+namespace {
+
+// ---------------------------------------------------------------- updates
+// 2D: iso  -> (h^2 f + ((W + E) + (S + N))) * 0.25      (Sec. 4.2, dx == dy)
+//     else -> (f + (wx (W + E) + wy (S + N))) * dinv    (Sec. 4.2 general form)
+template <typename T, bool ISO>
+__device__ __forceinline__ T upd2(T b, T w, T e, T s, T n, T wx, T wy, T dinv)
+{
+    if (ISO) return (b + ((w + e) + (s + n))) * T(0.25);
+    return (b + (wx * (w + e) + wy * (s + n))) * dinv;
+}
+
+// 1D: (h^2 f + (W + E)) * 0.5                            (Sec. 3.4)
+template <typename T>
+__device__ __forceinline__ T upd1(T bh, T w, T e)
+{
+    return (bh + (w + e)) * T(0.5);
+}
+
+// r = f - A x in FP64
+__device__ __forceinline__ double res2(double f, double x, double w, double e, double s, double n,
+                                       double wx, double wy)
+{
+    return f - (wx * ((2.0 * x - w) - e) + wy * ((2.0 * x - s) - n));
+}
+
+__device__ __forceinline__ double res1(double f, double x, double w, double e, double w1)
+{
+    return f - w1 * ((2.0 * x - w) - e);
+}
+
+constexpr int kNT = 256;  // threads per workgroup of every kernel here
+
+// ============================================================================
+// 2D hierarchical cycle: one workgroup per TX x TY tile, LDS ping-pong.
+// Thread t owns column t % TX of the tile and rows t / TX + j * (kNT / TX).
+// ============================================================================
+template <typename T, int TX, int TY, bool RES, bool ISO>
+__global__ __launch_bounds__(kNT) void k_cycle2d(Geom2 g, const T *__restrict__ f,
+                                                 const T *__restrict__ xin, T *__restrict__ xout,
+                                                 int s, double *__restrict__ partials, Ctrl *ctrl,
+                                                 double tol)
+{
+    static_assert(kNT % TX == 0 && (TX * TY) % kNT == 0, "tile/threads mismatch");
+    if (RES && ctrl->status != ST_RUNNING) return;
+
+    constexpr int P = TX + 2;          // LDS row pitch, halo column each side
+    constexpr int R = TY + 2;          // LDS rows, halo row each side
+    constexpr int PER = TX * TY / kNT; // points per thread
+    constexpr int RSTEP = kNT / TX;
+    __shared__ T buf[2][R * P];
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int bi = tile / g.ntx, bj = tile - bi * g.ntx;
+    const int r0 = axis_origin(g.ny, TY, g.oy, bi);
+    const int c0 = axis_origin(g.nx, TX, g.ox, bj);
+    const int ey = g.ny < TY ? g.ny : TY;
+    const int ex = g.nx < TX ? g.nx : TX;
+    const int64_t ld = g.ld;
+
+    // step 1: tile + one-point halo into both buffers (0 outside the domain)
+    for (int i = threadIdx.x; i < R * P; i += kNT) {
+        const int lr = i / P, lc = i - lr * P;
+        const int gr = r0 + lr - 1, gc = c0 + lc - 1;
+        T v = T(0);
+        if (gr >= 0 && gr < g.ny && gc >= 0 && gc < g.nx) v = xin[(int64_t)gr * ld + gc];
+        buf[0][i] = v;
+        buf[1][i] = v;
+    }
+
+    const int tc = threadIdx.x % TX, tr = threadIdx.x / TX;
+    const T hh = T(g.hh), wx = T(g.wx), wy = T(g.wy), dinv = T(g.dinv);
+    T fb[PER], val[PER];
+    double fr[RES ? PER : 1];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int r = tr + j * RSTEP;
+        T fv = T(0);
+        if (r < ey && tc < ex) fv = f[(int64_t)(r0 + r) * ld + c0 + tc];
+        fb[j] = ISO ? hh * fv : fv;
+        if (RES) fr[RES ? j : 0] = (double)fv;
+        val[j] = T(0);
+    }
+    const int rlo = axis_own_begin(g.ny, TY, g.oy, bi) - r0;
+    const int rhi = axis_own_end(g.ny, TY, g.oy, bi, g.nty) - r0;
+    const int clo = axis_own_begin(g.nx, TX, g.ox, bj) - c0;
+    const int chi = axis_own_end(g.nx, TX, g.ox, bj, g.ntx) - c0;
+    const bool col_own = tc >= clo && tc < chi;
+    __syncthreads();
+
+    // residual of the incoming iterate over the owned points
+    double rsq = 0.0;
+    if (RES) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int r = tr + j * RSTEP;
+            if (col_own && r >= rlo && r < rhi) {
+                const int a = (r + 1) * P + tc + 1;
+                const T *b0 = buf[0];
+                const double rr = res2(fr[RES ? j : 0], (double)b0[a], (double)b0[a - 1],
+                                       (double)b0[a + 1], (double)b0[a - P], (double)b0[a + P],
+                                       g.wx, g.wy);
+                rsq += rr * rr;
+            }
+        }
+    }
+
+    // step 2: s sub-iterations, halo untouched
+    for (int k = 0; k < s; ++k) {
+        const T *cur = buf[k & 1];
+        T *nxt = buf[(k & 1) ^ 1];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int r = tr + j * RSTEP;
+            if (r < ey && tc < ex) {
+                const int a = (r + 1) * P + tc + 1;
+                const T v = upd2<T, ISO>(fb[j], cur[a - 1], cur[a + 1], cur[a - P], cur[a + P],
+                                         wx, wy, dinv);
+                nxt[a] = v;
+                val[j] = v;
+            }
+        }
+        __syncthreads();
+    }
+
+    // step 3: owned interior points back to global memory
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int r = tr + j * RSTEP;
+        if (col_own && r >= rlo && r < rhi) xout[(int64_t)(r0 + r) * ld + c0 + tc] = val[j];
+    }
+
+    if (RES) grid_finalize<kNT>(rsq, partials, ctrl, -1, tol);
+}
+
+// ============================================================================
+// 2D classical sweep (global-memory Jacobi, Sec. 3.2 / 4.2): each thread walks
+// down RPT rows of one column, so x is read about once per point; W/E come
+// from the cache lines the neighbouring lanes fetch.
+// ============================================================================
+constexpr int kSBX = 64, kSBY = 4, kSRPT = 8;
+
+template <typename T, bool RES, bool ISO, bool SWEEP>
+__global__ __launch_bounds__(kNT) void k_sweep2d(Geom2 g, const T *__restrict__ f,
+                                                 const T *__restrict__ xin, T *__restrict__ xout,
+                                                 double *__restrict__ partials, Ctrl *ctrl,
+                                                 int64_t c_eval, double tol)
+{
+    if (SWEEP && RES && ctrl->status != ST_RUNNING) return;
+    const int gx = (g.nx + kSBX - 1) / kSBX;
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int by = b / gx, bx = b - by * gx;
+    const int c = bx * kSBX + (int)(threadIdx.x % kSBX);
+    const int rbeg = (by * kSBY + (int)(threadIdx.x / kSBX)) * kSRPT;
+    const int64_t ld = g.ld;
+    const T hh = T(g.hh), wx = T(g.wx), wy = T(g.wy), dinv = T(g.dinv);
+    double rsq = 0.0;
+    if (c < g.nx && rbeg < g.ny) {
+        T up = rbeg > 0 ? xin[(int64_t)(rbeg - 1) * ld + c] : T(0);
+        T cen = xin[(int64_t)rbeg * ld + c];
+#pragma unroll
+        for (int i = 0; i < kSRPT; ++i) {
+            const int r = rbeg + i;
+            if (r < g.ny) {
+                const int64_t a = (int64_t)r * ld + c;
+                const T dn = r + 1 < g.ny ? xin[a + ld] : T(0);
+                const T w = c > 0 ? xin[a - 1] : T(0);
+                const T e = c + 1 < g.nx ? xin[a + 1] : T(0);
+                const T fv = f[a];
+                if (SWEEP) xout[a] = upd2<T, ISO>(ISO ? hh * fv : fv, w, e, up, dn, wx, wy, dinv);
+                if (RES) {
+                    const double rr = res2((double)fv, (double)cen, (double)w, (double)e,
+                                           (double)up, (double)dn, g.wx, g.wy);
+                    if (!SWEEP && xout) xout[a] = (T)rr;  // residual kernel: optional r_out
+                    rsq += rr * rr;
+                }
+                up = cen;
+                cen = dn;
+            }
+        }
+    }
+    if (RES) grid_finalize<kNT>(rsq, partials, ctrl, c_eval, tol);
+}
+
+// ============================================================================
+// 1D hierarchical cycle.  Tiles of TT points; a workgroup holds G = kNT / TT
+// tiles (TT <= kNT) or one tile with TT / kNT points per thread.
+// ============================================================================
+template <typename T, int TT, bool RES>
+__global__ __launch_bounds__(kNT) void k_cycle1d(Geom1 g, const T *__restrict__ f,
+                                                 const T *__restrict__ xin, T *__restrict__ xout,
+                                                 int s, double *__restrict__ partials, Ctrl *ctrl,
+                                                 double tol)
+{
+    if (RES && ctrl->status != ST_RUNNING) return;
+    constexpr int G = TT <= kNT ? kNT / TT : 1;
+    constexpr int PER = TT <= kNT ? 1 : TT / kNT;
+    constexpr int P = TT + 2;
+    __shared__ T buf[2][G * P];
+
+    const int64_t blk = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t n = g.n;
+    const int ni = n < TT ? (int)n : TT;  // points per tile
+    const int ntile = (int)g.nt;
+    const int nint = n > 0x7fffffff ? 0x7fffffff : (int)n;
+
+    for (int i = threadIdx.x; i < G * P; i += kNT) {
+        const int gi = i / P, lc = i - gi * P;
+        const int64_t tile = blk * G + gi;
+        T v = T(0);
+        if (tile < ntile) {
+            const int64_t gp = (int64_t)axis_origin(nint, TT, g.o, (int)tile) + lc - 1;
+            if (gp >= 0 && gp < n) v = xin[gp];
+        }
+        buf[0][i] = v;
+        buf[1][i] = v;
+    }
+
+    const int gi = TT <= kNT ? (int)threadIdx.x / TT : 0;
+    const int64_t tile = blk * G + gi;
+    const bool live = tile < ntile;
+    const int64_t x0 = live ? axis_origin(nint, TT, g.o, (int)tile) : 0;
+    const int lo = live ? axis_own_begin(nint, TT, g.o, (int)tile) - (int)x0 : 0;
+    const int hi = live ? axis_own_end(nint, TT, g.o, (int)tile, ntile) - (int)x0 : 0;
+    const T hh = T(g.hh);
+    T fb[PER], val[PER];
+    double fr[RES ? PER : 1];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int lc = TT <= kNT ? (int)threadIdx.x % TT : (int)threadIdx.x + j * kNT;
+        T fv = T(0);
+        if (live && lc < ni) fv = f[x0 + lc];
+        fb[j] = hh * fv;
+        if (RES) fr[RES ? j : 0] = (double)fv;
+        val[j] = T(0);
+    }
+    __syncthreads();
+
+    double rsq = 0.0;
+    if (RES) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int lc = TT <= kNT ? (int)threadIdx.x % TT : (int)threadIdx.x + j * kNT;
+            if (live && lc >= lo && lc < hi) {
+                const int a = gi * P + lc + 1;
+                const double rr = res1(fr[RES ? j : 0], (double)buf[0][a], (double)buf[0][a - 1],
+                                       (double)buf[0][a + 1], g.w1);
+                rsq += rr * rr;
+            }
+        }
+    }
+
+    for (int k = 0; k < s; ++k) {
+        const T *cur = buf[k & 1];
+        T *nxt = buf[(k & 1) ^ 1];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int lc = TT <= kNT ? (int)threadIdx.x % TT : (int)threadIdx.x + j * kNT;
+            if (live && lc < ni) {
+                const int a = gi * P + lc + 1;
+                const T v = upd1<T>(fb[j], cur[a - 1], cur[a + 1]);
+                nxt[a] = v;
+                val[j] = v;
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int lc = TT <= kNT ? (int)threadIdx.x % TT : (int)threadIdx.x + j * kNT;
+        if (live && lc >= lo && lc < hi) xout[x0 + lc] = val[j];
+    }
+
+    if (RES) grid_finalize<kNT>(rsq, partials, ctrl, -1, tol);
+}
+
+// 1D classical sweep / residual: one point per thread.
+template <typename T, bool RES, bool SWEEP>
+__global__ __launch_bounds__(kNT) void k_sweep1d(Geom1 g, const T *__restrict__ f,
+                                                 const T *__restrict__ xin, T *__restrict__ xout,
+                                                 double *__restrict__ partials, Ctrl *ctrl,
+                                                 int64_t c_eval, double tol)
+{
+    if (SWEEP && RES && ctrl->status != ST_RUNNING) return;
+    const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kNT + threadIdx.x;
+    double rsq = 0.0;
+    if (i < g.n) {
+        const T w = i > 0 ? xin[i - 1] : T(0);
+        const T e = i + 1 < g.n ? xin[i + 1] : T(0);
+        const T fv = f[i];
+        if (SWEEP) xout[i] = upd1<T>(T(g.hh) * fv, w, e);
+        if (RES) {
+            const double rr = res1((double)fv, (double)xin[i], (double)w, (double)e, g.w1);
+            if (!SWEEP && xout) xout[i] = (T)rr;
+            rsq += rr * rr;
+        }
+    }
+    if (RES) grid_finalize<kNT>(rsq, partials, ctrl, c_eval, tol);
+}
+
+__global__ void k_ctrl_init(Ctrl *ctrl)
+{
+    ctrl->r0sq = 0.0;
+    ctrl->last_rsq = 0.0;
+    ctrl->iter = 0;
+    ctrl->done_cycle = -1;
+    ctrl->status = ST_RUNNING;
+    ctrl->arrive = 0u;
+}
+
+// ---------------------------------------------------------------- dispatch
+template <typename T, int TX, int TY>
+hipError_t cyc2(const Geom2 &g, int s, bool res, const void *f, const void *xin, void *xout,
+                double *part, Ctrl *ctrl, double tol, hipStream_t st)
+{
+    const unsigned nb = (unsigned)((int64_t)g.ntx * g.nty);
+    const T *F = (const T *)f;
+    const T *XI = (const T *)xin;
+    T *XO = (T *)xout;
+    if (res) {
+        if (g.iso) k_cycle2d<T, TX, TY, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, part, ctrl, tol);
+        else k_cycle2d<T, TX, TY, true, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, part, ctrl, tol);
+    } else {
+        if (g.iso) k_cycle2d<T, TX, TY, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, part, ctrl, tol);
+        else k_cycle2d<T, TX, TY, false, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, part, ctrl, tol);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t cyc2_t(const Geom2 &g, int s, bool res, const void *f, const void *xin, void *xout,
+                  double *part, Ctrl *ctrl, double tol, hipStream_t st)
+{
+#define HJ_TILE(a, b)                                                                     \
+    if (g.tx == a && g.ty == b) return cyc2<T, a, b>(g, s, res, f, xin, xout, part, ctrl, tol, st);
+    HJ_TILE(16, 16) HJ_TILE(16, 32) HJ_TILE(16, 64)
+    HJ_TILE(32, 16) HJ_TILE(32, 32) HJ_TILE(32, 64)
+    HJ_TILE(64, 16) HJ_TILE(64, 32) HJ_TILE(64, 64)
+#undef HJ_TILE
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int TT>
+hipError_t cyc1(const Geom1 &g, int s, bool res, const void *f, const void *xin, void *xout,
+                double *part, Ctrl *ctrl, double tol, hipStream_t st)
+{
+    constexpr int G = TT <= kNT ? kNT / TT : 1;
+    const unsigned nb = (unsigned)((g.nt + G - 1) / G);
+    if (res) k_cycle1d<T, TT, true><<<nb, kNT, 0, st>>>(g, (const T *)f, (const T *)xin, (T *)xout, s, part, ctrl, tol);
+    else k_cycle1d<T, TT, false><<<nb, kNT, 0, st>>>(g, (const T *)f, (const T *)xin, (T *)xout, s, part, ctrl, tol);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t cyc1_t(const Geom1 &g, int s, bool res, const void *f, const void *xin, void *xout,
+                  double *part, Ctrl *ctrl, double tol, hipStream_t st)
+{
+    switch (g.t) {
+    case 32: return cyc1<T, 32>(g, s, res, f, xin, xout, part, ctrl, tol, st);
+    case 64: return cyc1<T, 64>(g, s, res, f, xin, xout, part, ctrl, tol, st);
+    case 128: return cyc1<T, 128>(g, s, res, f, xin, xout, part, ctrl, tol, st);
+    case 256: return cyc1<T, 256>(g, s, res, f, xin, xout, part, ctrl, tol, st);
+    case 512: return cyc1<T, 512>(g, s, res, f, xin, xout, part, ctrl, tol, st);
+    case 1024: return cyc1<T, 1024>(g, s, res, f, xin, xout, part, ctrl, tol, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool cycle2d_supported(int tx, int ty)
+{
+    auto ok = [](int v) { return v == 16 || v == 32 || v == 64; };
+    return ok(tx) && ok(ty);
+}
+
+bool cycle1d_supported(int t)
+{
+    return t == 32 || t == 64 || t == 128 || t == 256 || t == 512 || t == 1024;
+}
+
+int64_t cycle2d_blocks(const Geom2 &g) { return (int64_t)g.ntx * g.nty; }
+
+int64_t sweep2d_blocks(const Geom2 &g)
+{
+    const int64_t gx = (g.nx + kSBX - 1) / kSBX;
+    const int64_t gy = (g.ny + kSBY * kSRPT - 1) / (kSBY * kSRPT);
+    return gx * gy;
+}
+
+int64_t resid2d_blocks(const Geom2 &g) { return sweep2d_blocks(g); }
+
+int64_t cycle1d_blocks(const Geom1 &g)
+{
+    const int64_t G = g.t <= kNT ? kNT / g.t : 1;
+    return (g.nt + G - 1) / G;
+}
+
+int64_t sweep1d_blocks(const Geom1 &g) { return (g.n + kNT - 1) / kNT; }
+int64_t resid1d_blocks(const Geom1 &g) { return sweep1d_blocks(g); }
+
+hipError_t launch_cycle2d(int dt, const Geom2 &g, int s, bool res, const void *f, const void *xin,
+                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st)
+{
+    if (dt == F64) return cyc2_t<double>(g, s, res, f, xin, xout, partials, ctrl, tol, st);
+    return cyc2_t<float>(g, s, res, f, xin, xout, partials, ctrl, tol, st);
+}
+
+template <typename T>
+static hipError_t sw2(const Geom2 &g, bool res, const void *f, const void *xin, void *xout,
+                      double *part, Ctrl *ctrl, double tol, hipStream_t st)
+{
+    const unsigned nb = (unsigned)sweep2d_blocks(g);
+    const T *F = (const T *)f;
+    const T *XI = (const T *)xin;
+    T *XO = (T *)xout;
+    if (res) {
+        if (g.iso) k_sweep2d<T, true, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, part, ctrl, -1, tol);
+        else k_sweep2d<T, true, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, part, ctrl, -1, tol);
+    } else {
+        if (g.iso) k_sweep2d<T, false, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, part, ctrl, -1, tol);
+        else k_sweep2d<T, false, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, part, ctrl, -1, tol);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep2d(int dt, const Geom2 &g, bool res, const void *f, const void *xin,
+                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st)
+{
+    if (dt == F64) return sw2<double>(g, res, f, xin, xout, partials, ctrl, tol, st);
+    return sw2<float>(g, res, f, xin, xout, partials, ctrl, tol, st);
+}
+
+hipError_t launch_resid2d(int dt, const Geom2 &g, const void *f, const void *x, void *r_out,
+                          double *partials, Ctrl *ctrl, int64_t c, double tol, hipStream_t st)
+{
+    const unsigned nb = (unsigned)sweep2d_blocks(g);
+    if (dt == F64)
+        k_sweep2d<double, true, true, false><<<nb, kNT, 0, st>>>(
+            g, (const double *)f, (const double *)x, (double *)r_out, partials, ctrl, c, tol);
+    else
+        k_sweep2d<float, true, true, false><<<nb, kNT, 0, st>>>(
+            g, (const float *)f, (const float *)x, (float *)r_out, partials, ctrl, c, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_cycle1d(int dt, const Geom1 &g, int s, bool res, const void *f, const void *xin,
+                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st)
+{
+    if (dt == F64) return cyc1_t<double>(g, s, res, f, xin, xout, partials, ctrl, tol, st);
+    return cyc1_t<float>(g, s, res, f, xin, xout, partials, ctrl, tol, st);
+}
+
+hipError_t launch_sweep1d(int dt, const Geom1 &g, bool res, const void *f, const void *xin,
+                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st)
+{
+    const unsigned nb = (unsigned)sweep1d_blocks(g);
+    if (dt == F64) {
+        if (res) k_sweep1d<double, true, true><<<nb, kNT, 0, st>>>(g, (const double *)f, (const double *)xin, (double *)xout, partials, ctrl, -1, tol);
+        else k_sweep1d<double, false, true><<<nb, kNT, 0, st>>>(g, (const double *)f, (const double *)xin, (double *)xout, partials, ctrl, -1, tol);
+    } else {
+        if (res) k_sweep1d<float, true, true><<<nb, kNT, 0, st>>>(g, (const float *)f, (const float *)xin, (float *)xout, partials, ctrl, -1, tol);
+        else k_sweep1d<float, false, true><<<nb, kNT, 0, st>>>(g, (const float *)f, (const float *)xin, (float *)xout, partials, ctrl, -1, tol);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_resid1d(int dt, const Geom1 &g, const void *f, const void *x, void *r_out,
+                          double *partials, Ctrl *ctrl, int64_t c, double tol, hipStream_t st)
+{
+    const unsigned nb = (unsigned)sweep1d_blocks(g);
+    if (dt == F64)
+        k_sweep1d<double, true, false><<<nb, kNT, 0, st>>>(g, (const double *)f, (const double *)x, (double *)r_out, partials, ctrl, c, tol);
+    else
+        k_sweep1d<float, true, false><<<nb, kNT, 0, st>>>(g, (const float *)f, (const float *)x, (float *)r_out, partials, ctrl, c, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctrl_init(Ctrl *ctrl, hipStream_t st)
+{
+    k_ctrl_init<<<1, 1, 0, st>>>(ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace hj

@@ -1,0 +1,63 @@
+// hj_launch.h -- host-side launchers of the HIP kernels (internal to libhj).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hj_device.h"
+
+namespace hj {
+
+enum Dtype : int { F64 = 0, F32 = 1 };
+
+// 2D problem geometry and coefficients (row-major, leading dimension ld).
+struct Geom2 {
+    int nx, ny;
+    int64_t ld;
+    int tx, ty, ox, oy;  // tile extents and overlaps
+    int ntx, nty;        // tiles per axis
+    int iso;             // hx == hy: use the h^2 f form of the update
+    double hh;           // h^2 (iso)
+    double wx, wy, dinv; // 1/hx^2, 1/hy^2, 1/(2wx + 2wy)
+};
+
+struct Geom1 {
+    int64_t n;
+    int t, o;
+    int64_t nt;          // tiles
+    double hh;           // h^2
+    double w1;           // 1/h^2
+};
+
+bool cycle2d_supported(int tx, int ty);
+bool cycle1d_supported(int t);
+
+// Number of workgroups (= reduction partials) each launcher uses.
+int64_t cycle2d_blocks(const Geom2 &g);
+int64_t sweep2d_blocks(const Geom2 &g);
+int64_t resid2d_blocks(const Geom2 &g);
+int64_t cycle1d_blocks(const Geom1 &g);
+int64_t sweep1d_blocks(const Geom1 &g);
+int64_t resid1d_blocks(const Geom1 &g);
+
+// One hierarchical cycle xin -> xout.  res: also reduce ||f - A xin||^2 and
+// judge iterate ctrl->iter against tol (skipped entirely once ctrl->status is set).
+hipError_t launch_cycle2d(int dt, const Geom2 &g, int s, bool res, const void *f, const void *xin,
+                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st);
+// One classical sweep over the whole grid, same residual contract.
+hipError_t launch_sweep2d(int dt, const Geom2 &g, bool res, const void *f, const void *xin,
+                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st);
+// Residual of x (optionally stored to r_out), judged as iterate c.
+hipError_t launch_resid2d(int dt, const Geom2 &g, const void *f, const void *x, void *r_out,
+                          double *partials, Ctrl *ctrl, int64_t c, double tol, hipStream_t st);
+
+hipError_t launch_cycle1d(int dt, const Geom1 &g, int s, bool res, const void *f, const void *xin,
+                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st);
+hipError_t launch_sweep1d(int dt, const Geom1 &g, bool res, const void *f, const void *xin,
+                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st);
+hipError_t launch_resid1d(int dt, const Geom1 &g, const void *f, const void *x, void *r_out,
+                          double *partials, Ctrl *ctrl, int64_t c, double tol, hipStream_t st);
+
+hipError_t launch_ctrl_init(Ctrl *ctrl, hipStream_t st);
+
+}  // namespace hj

@@ -1,0 +1,238 @@
+"""ctypes binding of libhj.so (include/hj.h): argument marshalling only.
+
+Every step of a solve runs in the HIP library; this module turns torch
+tensors into device pointers, sizes and the current HIP stream, and turns
+status codes into exceptions.  PyTorch supplies device memory and streams.
+
+    import torch
+    from paper_2006_16465_amd import hj
+    f = torch.randn(4096, 4096, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(f)
+    info = hj.solve_2d(f, x, h=1 / 4097, tile=(32, 32), s=16, rel_tol=1e-6)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhj.so")
+
+HJ_OK, HJ_ERR_INVALID_ARG, HJ_ERR_NOT_CONVERGED, HJ_ERR_NONFINITE, HJ_ERR_UNSUPPORTED, HJ_ERR_HIP = range(6)
+HJ_F64, HJ_F32 = 0, 1
+HJ_HIERARCHICAL, HJ_GLOBAL = 0, 1
+METHODS = {"hierarchical": HJ_HIERARCHICAL, "global": HJ_GLOBAL}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+        ("overlap_x", ctypes.c_int32), ("overlap_y", ctypes.c_int32),
+        ("s", ctypes.c_int32), ("method", ctypes.c_int32),
+        ("max_cycles", ctypes.c_int64), ("check_every", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("rel_tol", ctypes.c_double),
+    ]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int64), ("sweeps", ctypes.c_int64),
+                ("rel_residual", ctypes.c_double), ("r0_norm", ctypes.c_double)]
+
+
+@dataclass
+class Info:
+    status: int
+    cycles: int
+    sweeps: int
+    rel_residual: float
+    r0_norm: float
+
+    @property
+    def converged(self) -> bool:
+        return self.status == HJ_OK
+
+
+class HJError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{_status_name(status)}: {detail}")
+        self.status = status
+
+
+_lib = None
+EXPORTS = ("hj_params_default", "hj_solve_1d", "hj_solve_2d", "hj_residual", "hj_solve_batched",
+           "hj_solve_adjoint", "hj_axis_tiles", "hj_status_string", "hj_last_error", "hj_version")
+
+
+def load():
+    """Load libhj.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2006_16465_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64, i32, f64, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+    P, I = ctypes.POINTER(Params), ctypes.POINTER(_Info)
+    lib.hj_params_default.argtypes = [P]
+    lib.hj_params_default.restype = None
+    lib.hj_solve_1d.argtypes = [i64, f64, i32, vp, vp, P, vp, I]
+    lib.hj_solve_1d.restype = i32
+    lib.hj_solve_2d.argtypes = [i64, i64, i64, f64, f64, i32, vp, vp, P, vp, I]
+    lib.hj_solve_2d.restype = i32
+    lib.hj_residual.argtypes = [i32, i64, i64, i64, f64, f64, i32, vp, vp, vp, ctypes.POINTER(f64), vp]
+    lib.hj_residual.restype = i32
+    lib.hj_solve_batched.argtypes = [vp, i64, P, vp, vp]
+    lib.hj_solve_batched.restype = i32
+    lib.hj_solve_adjoint.argtypes = [vp, vp, vp]
+    lib.hj_solve_adjoint.restype = i32
+    lib.hj_axis_tiles.argtypes = [i64, i32, i32]
+    lib.hj_axis_tiles.restype = i64
+    lib.hj_status_string.argtypes = [i32]
+    lib.hj_status_string.restype = ctypes.c_char_p
+    lib.hj_last_error.argtypes = []
+    lib.hj_last_error.restype = ctypes.c_char_p
+    lib.hj_version.argtypes = []
+    lib.hj_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return load().hj_status_string(s).decode()
+    except Exception:
+        return f"status {s}"
+
+
+def last_error() -> str:
+    return load().hj_last_error().decode()
+
+
+def axis_tiles(n: int, tile: int, overlap: int = 0) -> int:
+    return int(load().hj_axis_tiles(n, tile, overlap))
+
+
+def make_params(tile=32, s=16, method="hierarchical", rel_tol=1e-6, max_cycles=1_000_000,
+                check_every=32, overlap=0) -> Params:
+    p = Params()
+    load().hj_params_default(ctypes.byref(p))
+    tx, ty = (tile, tile) if isinstance(tile, int) else tile
+    ox, oy = (overlap, overlap) if isinstance(overlap, int) else overlap
+    p.tile_x, p.tile_y, p.overlap_x, p.overlap_y = tx, ty, ox, oy
+    p.s = s
+    p.method = METHODS[method] if isinstance(method, str) else int(method)
+    p.rel_tol = rel_tol
+    p.max_cycles = max_cycles
+    p.check_every = check_every
+    return p
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return HJ_F64
+    if t.dtype == torch.float32:
+        return HJ_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _check_pair(f, x):
+    if not (f.is_cuda and x.is_cuda):
+        raise ValueError("f and x must be GPU tensors")
+    if f.dtype != x.dtype or f.shape != x.shape:
+        raise ValueError("f and x must share dtype and shape")
+
+
+def _ld(t) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("2D tensors must be row-major with unit column stride")
+    return t.stride(0)
+
+
+def _raise_or_info(st: int, info: _Info, allow_not_converged: bool) -> Info:
+    out = Info(st, info.cycles, info.sweeps, info.rel_residual, info.r0_norm)
+    if st == HJ_OK or (st == HJ_ERR_NOT_CONVERGED and allow_not_converged):
+        return out
+    raise HJError(st, last_error())
+
+
+def solve_1d(f, x, h, *, tile=32, s=16, method="hierarchical", rel_tol=1e-6, max_cycles=1_000_000,
+             check_every=32, overlap=0, allow_not_converged=False) -> Info:
+    """Solve -u'' = f (n interior points, spacing h) in place in x (hj_solve_1d)."""
+    _check_pair(f, x)
+    if f.dim() != 1 or not f.is_contiguous() or not x.is_contiguous():
+        raise ValueError("1D tensors must be contiguous vectors")
+    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap)
+    info = _Info()
+    with _device(f):
+        st = load().hj_solve_1d(f.numel(), float(h), _dtype_code(f), f.data_ptr(), x.data_ptr(),
+                                ctypes.byref(p), _stream(f), ctypes.byref(info))
+    return _raise_or_info(st, info, allow_not_converged)
+
+
+def solve_2d(f, x, h=None, *, hx=None, hy=None, tile=(32, 32), s=16, method="hierarchical",
+             rel_tol=1e-6, max_cycles=1_000_000, check_every=32, overlap=(0, 0),
+             allow_not_converged=False) -> Info:
+    """Solve the 5-point Poisson system in place in x, f and x of shape (ny, nx) (hj_solve_2d)."""
+    _check_pair(f, x)
+    hx = hx if hx is not None else h
+    hy = hy if hy is not None else hx
+    ld = _ld(f)
+    if _ld(x) != ld:
+        raise ValueError("f and x must share the row stride")
+    ny, nx = f.shape
+    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap)
+    info = _Info()
+    with _device(f):
+        st = load().hj_solve_2d(nx, ny, ld, float(hx), float(hy), _dtype_code(f), f.data_ptr(),
+                                x.data_ptr(), ctypes.byref(p), _stream(f), ctypes.byref(info))
+    return _raise_or_info(st, info, allow_not_converged)
+
+
+def residual(f, x, h=None, *, hx=None, hy=None, r_out=None) -> float:
+    """||f - A x||_2 (FP64); fills r_out with f - A x when given (hj_residual)."""
+    _check_pair(f, x)
+    hx = hx if hx is not None else h
+    hy = hy if hy is not None else hx
+    if r_out is not None and (r_out.dtype != f.dtype or r_out.shape != f.shape or not r_out.is_cuda):
+        raise ValueError("r_out must match f")
+    nrm = ctypes.c_double(0.0)
+    rp = r_out.data_ptr() if r_out is not None else None
+    with _device(f):
+        if f.dim() == 1:
+            st = load().hj_residual(1, f.numel(), 1, f.numel(), float(hx), float(hx), _dtype_code(f),
+                                    f.data_ptr(), x.data_ptr(), rp, ctypes.byref(nrm), _stream(f))
+        else:
+            ld = _ld(f)
+            if _ld(x) != ld or (r_out is not None and _ld(r_out) != ld):
+                raise ValueError("f, x and r_out must share the row stride")
+            ny, nx = f.shape
+            st = load().hj_residual(2, nx, ny, ld, float(hx), float(hy), _dtype_code(f),
+                                    f.data_ptr(), x.data_ptr(), rp, ctypes.byref(nrm), _stream(f))
+    if st != HJ_OK:
+        raise HJError(st, last_error())
+    return nrm.value
+
+
+class _device:
+    """Make the tensor's GPU current for the duration of a library call."""
+
+    def __init__(self, t):
+        self.idx = t.device.index
+
+    def __enter__(self):
+        import torch
+        self.prev = torch.cuda.current_device()
+        if self.idx is not None and self.idx != self.prev:
+            torch.cuda.set_device(self.idx)
+
+    def __exit__(self, *a):
+        import torch
+        if self.idx is not None and self.idx != self.prev:
+            torch.cuda.set_device(self.prev)

@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point include/hj.h declares, and rejects invalid arguments before touching
+the HIP runtime."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2006_16465_amd import hj
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hj.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hj_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("hj_solve_1d", "hj_solve_2d", "hj_residual", "hj_solve_batched", "hj_solve_adjoint"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = hj.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(hj.EXPORTS) == set(declared_functions())
+
+
+def _params(**kw):
+    p = hj.Params()
+    hj.load().hj_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+FAKE = 0x10000  # aligned non-NULL pointer; validation must reject before it is used
+
+
+@pytest.mark.parametrize("args,kw,code", [
+    ((0, 8, 8, 0.1, 0.1, 0), {}, hj.HJ_ERR_INVALID_ARG),         # nx = 0
+    ((8, 0, 8, 0.1, 0.1, 0), {}, hj.HJ_ERR_INVALID_ARG),         # ny = 0
+    ((8, 8, 7, 0.1, 0.1, 0), {}, hj.HJ_ERR_INVALID_ARG),         # ld < nx
+    ((8, 8, 8, 0.0, 0.1, 0), {}, hj.HJ_ERR_INVALID_ARG),         # hx = 0
+    ((8, 8, 8, 0.1, float("nan"), 0), {}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 7), {}, hj.HJ_ERR_INVALID_ARG),         # dtype
+    ((8, 8, 8, 0.1, 0.1, 0), {"s": 0}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 0), {"max_cycles": 0}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 0), {"overlap_x": 32}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 0), {"overlap_y": -2}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 0), {"method": 5}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 0), {"flags": 1}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 0), {"rel_tol": float("nan")}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 0), {"tile_x": 48}, hj.HJ_ERR_UNSUPPORTED),
+    ((8, 8, 8, 0.1, 0.1, 0), {"tile_y": 128}, hj.HJ_ERR_UNSUPPORTED),
+])
+def test_solve_2d_rejects_invalid_arguments(args, kw, code):
+    lib = hj.load()
+    info = hj._Info()
+    p = _params(**kw)
+    st = lib.hj_solve_2d(*args, FAKE, FAKE, ctypes.byref(p), None, ctypes.byref(info))
+    assert st == code, hj.last_error()
+    assert hj.last_error()
+
+
+def test_solve_rejects_null_and_misaligned_pointers():
+    lib = hj.load()
+    info = hj._Info()
+    p = _params()
+    assert lib.hj_solve_2d(8, 8, 8, 0.1, 0.1, 0, None, FAKE, ctypes.byref(p), None, ctypes.byref(info)) == 1
+    assert lib.hj_solve_2d(8, 8, 8, 0.1, 0.1, 0, FAKE + 4, FAKE, ctypes.byref(p), None, ctypes.byref(info)) == 1
+    assert lib.hj_solve_2d(8, 8, 8, 0.1, 0.1, 0, FAKE, FAKE, None, None, ctypes.byref(info)) == 1
+    assert lib.hj_solve_1d(0, 0.1, 0, FAKE, FAKE, ctypes.byref(p), None, ctypes.byref(info)) == 1
+    assert lib.hj_solve_1d(16, -1.0, 0, FAKE, FAKE, ctypes.byref(p), None, ctypes.byref(info)) == 1
+    p1 = _params(tile_x=48)
+    assert lib.hj_solve_1d(16, 0.1, 0, FAKE, FAKE, ctypes.byref(p1), None, ctypes.byref(info)) == hj.HJ_ERR_UNSUPPORTED
+    nrm = ctypes.c_double()
+    assert lib.hj_residual(3, 8, 8, 8, 0.1, 0.1, 0, FAKE, FAKE, None, ctypes.byref(nrm), None) == 1
+    assert lib.hj_residual(2, 8, 8, 4, 0.1, 0.1, 0, FAKE, FAKE, None, ctypes.byref(nrm), None) == 1
+    assert lib.hj_residual(2, 8, 8, 8, 0.1, 0.1, 0, FAKE, FAKE, FAKE + 2, ctypes.byref(nrm), None) == 1
+
+
+def test_future_entry_points_report_unsupported():
+    lib = hj.load()
+    p = _params()
+    assert lib.hj_solve_batched(None, 0, ctypes.byref(p), None, None) == hj.HJ_ERR_UNSUPPORTED
+    assert lib.hj_solve_adjoint(None, None, None) == hj.HJ_ERR_UNSUPPORTED
+
+
+def test_status_strings_and_defaults():
+    lib = hj.load()
+    assert lib.hj_status_string(0) == b"HJ_OK"
+    assert lib.hj_status_string(2) == b"HJ_ERR_NOT_CONVERGED"
+    p = _params()
+    assert (p.tile_x, p.tile_y, p.s, p.method, p.check_every) == (32, 32, 16, 0, 32)
+    assert p.rel_tol == 1e-6 and p.flags == 0
+
+
+@pytest.mark.parametrize("n,t,o", [(4096, 32, 0), (4096, 32, 4), (1000, 64, 6), (7, 32, 0), (12, 4, 2)])
+def test_partition_count_agrees_with_oracle(orc, n, t, o):
+    assert hj.axis_tiles(n, t, o) == len(orc.axis_tiles(n, t, o))
+    assert hj.axis_tiles(0, 32, 0) == -1 and hj.axis_tiles(10, 8, 8) == -1

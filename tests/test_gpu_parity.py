@@ -1,0 +1,335 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle on
+the same seeded inputs.  FP64 iterates must agree within 1e-12 relative (the
+kernels use the same update association and no FMA contraction, so they are
+expected to agree bit for bit); FP32 iterates within 1e-5 relative of the FP64
+oracle; cycles-to-tolerance must be equal."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2006_16465_amd import hj
+from paper_2006_16465_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    hj.load()
+    yield
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def gpu_cycles_2d(f, x0, h, tile, s, ncyc, overlap=(0, 0), dtype=torch.float64, method="hierarchical",
+                  hy=None):
+    F, X = dev(f, dtype), dev(x0, dtype)
+    info = hj.solve_2d(F, X, hx=h, hy=hy if hy else h, tile=tile, s=s, overlap=overlap, method=method,
+                       rel_tol=0.0, max_cycles=ncyc)
+    assert info.cycles == ncyc
+    return host(X), info
+
+
+def gpu_cycles_1d(f, x0, h, tile, s, ncyc, overlap=0, dtype=torch.float64, method="hierarchical"):
+    F, X = dev(f, dtype), dev(x0, dtype)
+    info = hj.solve_1d(F, X, h, tile=tile, s=s, overlap=overlap, method=method, rel_tol=0.0,
+                       max_cycles=ncyc)
+    assert info.cycles == ncyc
+    return host(X), info
+
+
+# ------------------------------------------------------------------ 2D cycles, fixed counts
+
+@pytest.mark.parametrize("s", [1, 4, 8, 16, 32])
+def test_cycle2d_512_all_s_matches_oracle(orc, s):
+    f, h = W.make("poisson2d_512", 0)
+    x0 = np.zeros_like(f)
+    for nc in (1, 2, 7, 64):
+        say(f"cycle2d 512^2 s={s} cycles={nc}")
+        got, info = gpu_cycles_2d(f, x0, h, (32, 32), s, nc)
+        want = orc.hier_2d(f, x0, h, h, (32, 32), s, nc)
+        assert rel(got, want) <= 1e-12
+        assert np.array_equal(got, want), "FP64 iterates expected bit-identical"
+        assert info.sweeps == nc * s
+
+
+@pytest.mark.parametrize("shape", [(77, 100), (65, 33), (3, 5), (64, 130), (1, 40)])
+@pytest.mark.parametrize("tile", [(32, 32), (64, 16), (16, 64)])
+@pytest.mark.parametrize("overlap", [(0, 0), (4, 2), (10, 6)])
+def test_cycle2d_ragged_and_overlap(orc, shape, tile, overlap):
+    ny, nx = shape
+    f = W.rhs_random(shape, nx * 31 + ny)
+    x0 = W.rhs_random(shape, nx * 37 + ny)
+    h = 1.0 / (max(nx, ny) + 1)
+    ov = (min(overlap[0], tile[0] - 2), min(overlap[1], tile[1] - 2))
+    for s, nc in ((1, 3), (3, 1), (16, 5)):
+        say(f"cycle2d ragged {shape} tile={tile} ov={ov} s={s} nc={nc}")
+        got, _ = gpu_cycles_2d(f, x0, h, tile, s, nc, ov)
+        want = orc.hier_2d(f, x0, h, h, tile, s, nc, ov)
+        assert np.array_equal(got, want)
+
+
+def test_cycle2d_anisotropic_spacing(orc):
+    ny, nx = 96, 130
+    f = W.rhs_random((ny, nx), 5)
+    x0 = W.rhs_random((ny, nx), 6)
+    hx, hy = 1.0 / 131, 1.0 / 61
+    for tile, s, nc in (((32, 32), 8, 4), ((64, 16), 5, 3)):
+        say(f"cycle2d aniso tile={tile} s={s}")
+        got, _ = gpu_cycles_2d(f, x0, hx, tile, s, nc, hy=hy)
+        want = orc.hier_2d(f, x0, hx, hy, tile, s, nc)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("shape", [(512, 512), (77, 100), (1, 1), (200, 3)])
+def test_global_sweep_2d_matches_oracle(orc, shape):
+    f = W.rhs_random(shape, 41)
+    x0 = W.rhs_random(shape, 42)
+    h = 1.0 / (max(shape) + 1)
+    for nc in (1, 7, 64):
+        say(f"sweep2d {shape} sweeps={nc}")
+        got, info = gpu_cycles_2d(f, x0, h, (32, 32), 1, nc, method="global")
+        assert np.array_equal(got, orc.jacobi_2d(f, x0, h, h, nc))
+        assert info.sweeps == nc
+
+
+# ------------------------------------------------------------------ 1D
+
+@pytest.mark.parametrize("n", [256, 1000, 37, 5, 3000])
+@pytest.mark.parametrize("tile", [32, 64, 256, 1024])
+@pytest.mark.parametrize("overlap", [0, 4, 10])
+def test_cycle1d_matches_oracle(orc, n, tile, overlap):
+    f = W.rhs_random(n, n + tile)
+    x0 = W.rhs_random(n, n + tile + 1)
+    h = 1.0 / (n + 1)
+    for s, nc in ((1, 4), (16, 3), (5, 9)):
+        say(f"cycle1d n={n} tile={tile} ov={overlap} s={s} nc={nc}")
+        got, _ = gpu_cycles_1d(f, x0, h, tile, s, nc, overlap)
+        assert np.array_equal(got, orc.hier_1d(f, x0, h, tile, s, nc, overlap))
+
+
+@pytest.mark.parametrize("n", [256, 1, 2, 1025, 100000])
+def test_global_sweep_1d_matches_oracle(orc, n):
+    f = W.rhs_random(n, 3)
+    x0 = W.rhs_random(n, 4)
+    h = 1.0 / (n + 1)
+    for nc in (1, 10):
+        got, _ = gpu_cycles_1d(f, x0, h, 32, 1, nc, method="global")
+        assert np.array_equal(got, orc.jacobi_1d(f, x0, h, nc))
+
+
+# ------------------------------------------------------------------ residual
+
+@pytest.mark.parametrize("shape", [(512, 512), (33, 70), (1, 1)])
+def test_residual_2d_matches_oracle(orc, shape):
+    f = W.rhs_random(shape, 51)
+    x = W.rhs_random(shape, 52)
+    hx, hy = 1.0 / (shape[1] + 1), 1.0 / (shape[0] + 1)
+    F, X = dev(f), dev(x)
+    R = torch.empty_like(F)
+    nrm = hj.residual(F, X, hx=hx, hy=hy, r_out=R)
+    r, nw = orc.residual_2d(f, x, hx, hy)
+    assert abs(nrm - nw) <= 1e-12 * nw
+    assert np.max(np.abs(host(R) - r)) <= 1e-12 * np.max(np.abs(r))
+
+
+def test_residual_1d_matches_oracle(orc):
+    n = 10007
+    f, x = W.rhs_random(n, 61), W.rhs_random(n, 62)
+    h = 1.0 / (n + 1)
+    F, X = dev(f), dev(x)
+    R = torch.empty_like(F)
+    nrm = hj.residual(F, X, h, r_out=R)
+    r, nw = orc.residual_1d(f, x, h)
+    assert abs(nrm - nw) <= 1e-12 * nw
+    assert np.max(np.abs(host(R) - r)) <= 1e-12 * np.max(np.abs(r))
+
+
+# ------------------------------------------------------------------ solve to tolerance
+
+@pytest.mark.parametrize("seed", range(5))
+def test_solve_1d_cycles_to_tol_match_oracle(orc, seed):
+    f, h = W.make("poisson1d_n256", seed)
+    x0 = np.zeros_like(f)
+    for method, om in (("hierarchical", orc.HIERARCHICAL), ("global", orc.CLASSICAL)):
+        say(f"solve1d n=256 seed={seed} {method}")
+        X = dev(x0)
+        info = hj.solve_1d(dev(f), X, h, tile=32, s=16, method=method, rel_tol=1e-6)
+        xo, co, relo, r0o = orc.solve_1d(f, x0, h, method=om, tile=32, s=16, tol=1e-6)
+        assert info.cycles == co
+        assert np.array_equal(host(X), xo)
+        assert abs(info.rel_residual - relo) <= 1e-12 * relo
+        assert abs(info.r0_norm - r0o) <= 1e-12 * r0o
+
+
+@pytest.mark.parametrize("s,tile,ov", [(8, (32, 32), (0, 0)), (16, (32, 32), (0, 0)), (4, (16, 16), (2, 2))])
+def test_solve_2d_cycles_to_tol_match_oracle(orc, s, tile, ov):
+    f = W.rhs_2d_modes(128, 128, 16, 0.1, 3)
+    h = 1.0 / 129
+    x0 = np.zeros_like(f)
+    X = dev(x0)
+    say(f"solve2d 128^2 s={s} tile={tile} ov={ov}")
+    info = hj.solve_2d(dev(f), X, h, tile=tile, s=s, overlap=ov, rel_tol=1e-6, check_every=7)
+    xo, co, relo, _ = orc.solve_2d(f, x0, h, h, tile=tile, s=s, tol=1e-6, overlap=ov)
+    assert info.cycles == co > 0
+    assert np.array_equal(host(X), xo)
+    assert abs(info.rel_residual - relo) <= 1e-12 * relo
+
+
+def test_solve_2d_global_cycles_to_tol_match_oracle(orc):
+    f = W.rhs_2d_modes(96, 96, 8, 0.0, 1)
+    h = 1.0 / 97
+    x0 = np.zeros_like(f)
+    X = dev(x0)
+    info = hj.solve_2d(dev(f), X, h, method="global", rel_tol=1e-6)
+    xo, co, _, _ = orc.solve_2d(f, x0, h, h, method=orc.CLASSICAL, tol=1e-6)
+    assert info.cycles == co > 0
+    assert np.array_equal(host(X), xo)
+
+
+# ------------------------------------------------------------------ full size 4096^2
+
+def test_4096_fixed_cycles_and_determinism(orc):
+    f, h = W.make("poisson2d_4096", 2)
+    x0 = np.zeros_like(f)
+    say("4096^2 fixed 2 cycles T=32 s=16")
+    got, _ = gpu_cycles_2d(f, x0, h, (32, 32), 16, 2)
+    want = orc.hier_2d(f, x0, h, h, (32, 32), 16, 2)
+    assert np.array_equal(got, want)
+    got2, _ = gpu_cycles_2d(f, x0, h, (32, 32), 16, 2)
+    assert np.array_equal(got, got2)
+
+
+def test_4096_time_to_tolerance_workload_matches_oracle(orc):
+    """The timed workload: 4096^2, 8 separable modes, T=32, s=16, to 1e-6."""
+    f, h = W.make("poisson2d_4096", 2)
+    x0 = np.zeros_like(f)
+    X = dev(x0)
+    say("4096^2 solve to 1e-6 (GPU)")
+    info = hj.solve_2d(dev(f), X, h, tile=(32, 32), s=16, rel_tol=1e-6)
+    say(f"  gpu cycles={info.cycles}; oracle solve ...")
+    xo, co, relo, _ = orc.solve_2d(f, x0, h, h, tile=(32, 32), s=16, tol=1e-6, max_cycles=5000)
+    assert info.cycles == co
+    assert np.array_equal(host(X), xo)
+    assert abs(info.rel_residual - relo) <= 1e-12 * relo
+    say("4096^2 global solve to 1e-6, seed 0")
+    f0, _ = W.make("poisson2d_4096", 0)
+    X0 = dev(x0)
+    info0 = hj.solve_2d(dev(f0), X0, h, method="global", rel_tol=1e-6)
+    xo0, co0, _, _ = orc.solve_2d(f0, x0, h, h, method=orc.CLASSICAL, tol=1e-6, max_cycles=5000)
+    assert info0.cycles == co0
+    assert np.array_equal(host(X0), xo0)
+
+
+# ------------------------------------------------------------------ contracts
+
+def test_resume_equals_one_longer_run():
+    f, h = W.make("poisson2d_512", 1)
+    a, _ = gpu_cycles_2d(f, np.zeros_like(f), h, (32, 32), 8, 40)
+    b, _ = gpu_cycles_2d(f, np.zeros_like(f), h, (32, 32), 8, 20)
+    b, _ = gpu_cycles_2d(f, b, h, (32, 32), 8, 20)
+    assert np.array_equal(a, b)
+
+
+def test_not_converged_returns_last_iterate(orc):
+    f, h = W.make("poisson2d_512", 0)
+    x0 = np.zeros_like(f)
+    X = dev(x0)
+    info = hj.solve_2d(dev(f), X, h, s=8, rel_tol=1e-12, max_cycles=5, allow_not_converged=True)
+    assert info.status == hj.HJ_ERR_NOT_CONVERGED and info.cycles == 5
+    want = orc.hier_2d(f, x0, h, h, (32, 32), 8, 5)
+    assert np.array_equal(host(X), want)
+    _, nr = orc.residual_2d(f, want, h, h)
+    _, n0 = orc.residual_2d(f, x0, h, h)
+    assert abs(info.rel_residual - nr / n0) <= 1e-12 * (nr / n0)
+    with pytest.raises(hj.HJError):
+        hj.solve_2d(dev(f), dev(x0), h, s=8, rel_tol=1e-12, max_cycles=3)
+
+
+def test_nonfinite_rhs_is_reported():
+    f = W.rhs_random((64, 64), 1)
+    f[10, 20] = np.nan
+    with pytest.raises(hj.HJError) as e:
+        hj.solve_2d(dev(f), dev(np.zeros_like(f)), 1 / 65, rel_tol=1e-6)
+    assert e.value.status == hj.HJ_ERR_NONFINITE
+
+
+def test_zero_rhs_converges_at_cycle_zero():
+    X = dev(np.zeros((64, 64)))
+    info = hj.solve_2d(dev(np.zeros((64, 64))), X, 1 / 65, rel_tol=1e-6)
+    assert info.cycles == 0 and info.rel_residual == 0.0
+
+
+def test_host_pointer_is_rejected():
+    lib = hj.load()
+    a = np.zeros(64 * 64)
+    p = hj.make_params()
+    info = hj._Info()
+    ptr = a.ctypes.data
+    st = lib.hj_solve_2d(64, 64, 64, 1 / 65, 1 / 65, 0, ptr, ptr, ctypes.byref(p), None, ctypes.byref(info))
+    assert st == hj.HJ_ERR_INVALID_ARG
+
+
+def test_pitched_rows_leave_padding_untouched(orc):
+    ny, nx, ld = 70, 90, 97
+    f = W.rhs_random((ny, nx), 71)
+    x0 = W.rhs_random((ny, nx), 72)
+    h = 1.0 / 91
+    Fp = torch.full((ny, ld), 7.0, dtype=torch.float64, device="cuda")
+    Xp = torch.full((ny, ld), -3.0, dtype=torch.float64, device="cuda")
+    Fp[:, :nx] = dev(f)
+    Xp[:, :nx] = dev(x0)
+    F, X = Fp[:, :nx], Xp[:, :nx]
+    hj.solve_2d(F, X, h, tile=(32, 32), s=5, rel_tol=0.0, max_cycles=3)
+    out = host(Xp)
+    assert np.array_equal(out[:, :nx], orc.hier_2d(f, x0, h, h, (32, 32), 5, 3))
+    assert np.all(out[:, nx:] == -3.0)
+
+
+def test_side_stream(orc):
+    f, h = W.make("poisson2d_512", 2)
+    x0 = np.zeros_like(f)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        F, X = dev(f), dev(x0)
+        hj.solve_2d(F, X, h, s=4, rel_tol=0.0, max_cycles=6)
+    s.synchronize()
+    assert np.array_equal(host(X), orc.hier_2d(f, x0, h, h, (32, 32), 4, 6))
+
+
+# ------------------------------------------------------------------ FP32 instantiation
+
+def test_fp32_iterates_within_1e5_of_fp64_oracle(orc):
+    f, h = W.make("poisson2d_512", 0)
+    x0 = np.zeros_like(f)
+    for s, nc in ((16, 64), (4, 200)):
+        got, _ = gpu_cycles_2d(f, x0, h, (32, 32), s, nc, dtype=torch.float32)
+        want = orc.hier_2d(f, x0, h, h, (32, 32), s, nc)
+        e = rel(got, want)
+        say(f"fp32 512^2 s={s} cycles={nc}: rel err vs fp64 oracle {e:.3e}")
+        assert e <= 1e-5
+    n = 1000
+    f1 = W.rhs_1d_modes(n, 8, 1)
+    got, _ = gpu_cycles_1d(f1, np.zeros(n), 1 / (n + 1), 64, 16, 50, dtype=torch.float32)
+    assert rel(got, orc.hier_1d(f1, np.zeros(n), 1 / (n + 1), 64, 16, 50)) <= 1e-5
