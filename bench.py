@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-global", action="store_true", help="skip the global-memory baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample budget")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -96,6 +98,9 @@ def main():
     from paper_2006_16465_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        calibrate_copy(torch)
+        return
     hj.load()
     dev = torch.device("cuda:0")
     n = args.n
@@ -215,6 +220,19 @@ def main():
         **extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def calibrate_copy(torch):
+    """A plain copy of 2^27 doubles (1 GiB read + 1 GiB written) three times,
+    to scale FETCH_SIZE / WRITE_SIZE counter readings to bytes."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                      "launches": 3}), flush=True)
 
 
 def cpu_baseline(args, W, cycles_h, tile, ov, s):

@@ -87,6 +87,10 @@ typedef enum hj_dtype { HJ_F64 = 0, HJ_F32 = 1 } hj_dtype;
 
 typedef enum hj_method { HJ_HIERARCHICAL = 0, HJ_GLOBAL = 1 } hj_method;
 
+/* hj_params.flags: run every 2D cycle on the LDS ping-pong kernel instead of
+ * the register-resident one (same iterates; for comparison and testing). */
+#define HJ_FLAG_LDS_KERNEL 0x1
+
 typedef struct hj_params {
     int32_t tile_x;      /* interior tile extent along x (1D: the tile); 0 = 32.
                             2D supports 16, 32, 64; 1D supports 32..1024 (powers of 2) */
@@ -98,7 +102,7 @@ typedef struct hj_params {
     int64_t max_cycles;  /* >= 1: cycles (HJ_GLOBAL: sweeps) allowed */
     int32_t check_every; /* cycles enqueued between host polls of the device-side
                             convergence flag; 0 = 32.  Does not change results. */
-    int32_t flags;       /* must be 0 */
+    int32_t flags;       /* 0, or HJ_FLAG_LDS_KERNEL */
     double rel_tol;      /* > 0: stop at the first cycle c with ||r_c|| <= rel_tol ||r_0||.
                             <= 0: run exactly max_cycles cycles with no residual
                             evaluation in between (fixed-count mode). */

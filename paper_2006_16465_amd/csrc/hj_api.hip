@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <functional>
 #include <mutex>
@@ -96,7 +97,7 @@ hj_status check_ptr_dtype(const void *p, hj_dtype dt, const char *name, bool may
 hj_status check_params(const hj_params *p, int dim)
 {
     if (!p) return fail(HJ_ERR_INVALID_ARG, "params is NULL");
-    if (p->flags != 0) return fail(HJ_ERR_INVALID_ARG, "params.flags must be 0");
+    if (p->flags & ~HJ_FLAG_LDS_KERNEL) return fail(HJ_ERR_INVALID_ARG, "unknown bits in params.flags");
     if (p->method != HJ_HIERARCHICAL && p->method != HJ_GLOBAL)
         return fail(HJ_ERR_INVALID_ARG, "params.method must be HJ_HIERARCHICAL or HJ_GLOBAL");
     if (p->max_cycles < 1) return fail(HJ_ERR_INVALID_ARG, "params.max_cycles must be >= 1");
@@ -139,31 +140,50 @@ hj_status check_device_ptr(const void *p, int dev, const char *name)
 }
 
 // ---------------------------------------------------------------- driver
+// Iterates rotate through three arrays (the caller's x and two scratch
+// arrays): cycle c reads bufs[c % 3] and writes bufs[(c + 1) % 3].  The verdict
+// on iterate c is reached inside cycle kernel c + 1, which is still allowed to
+// run, so the converged iterate must survive two more writes.
 struct Step {
-    // one cycle reading xin writing xout; res = fused residual of xin
-    std::function<hipError_t(const void *, void *, bool, double)> cycle;
-    // residual of x judged as iterate c
-    std::function<hipError_t(const void *, int64_t, double)> resid;
-    // copy scratch -> user x
+    // one cycle xin -> xout; res: fused residual of xin under red
+    std::function<hipError_t(const void *, void *, bool, double, const hj::Red &)> cycle;
+    // residual of x, partial sums into part
+    std::function<hipError_t(const void *, double *)> resid;
+    // copy an iterate into the caller's x
     std::function<hipError_t(void *, const void *)> copy;
+    int nb_cycle;  // workgroups of one cycle kernel
+    int nb_resid;  // workgroups of the residual kernel
 };
 
-hj_status drive(const Step &st, void *xu, void *xs, const hj_params &p, int64_t spc,
+hj_status read_ctrl(DevScratch &S, hipStream_t stream, hj::Ctrl &c)
+{
+    HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
+    HJ_HIP(hipStreamSynchronize(stream));
+    c = S.host[0];
+    return HJ_OK;
+}
+
+hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_params &p, int64_t spc,
                 hipStream_t stream, DevScratch &S, hj_info *info)
 {
-    void *bufs[2] = {xu, xs};
+    void *bufs[3] = {xu, xs, (char *)xs + xbytes};
+    double *part[2] = {S.partials, S.partials + S.npart / 2};
     const int64_t maxc = p.max_cycles;
     const int batch = p.check_every > 0 ? p.check_every : 32;
+    hj_status r;
     HJ_HIP(hj::launch_ctrl_init(S.ctrl, stream));
     int64_t final_c = maxc;
     hj::Ctrl c{};
     if (p.rel_tol <= 0.0) {
-        HJ_HIP(st.resid(bufs[0], 0, -1.0));
-        for (int64_t k = 0; k < maxc; ++k) HJ_HIP(st.cycle(bufs[k & 1], bufs[(k + 1) & 1], false, -1.0));
-        HJ_HIP(st.resid(bufs[maxc & 1], maxc, -1.0));
-        HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
-        HJ_HIP(hipStreamSynchronize(stream));
-        c = S.host[0];
+        // fixed count: residuals of x_0 and x_maxc only
+        HJ_HIP(st.resid(bufs[0], part[0]));
+        HJ_HIP(hj::launch_judge(part[0], st.nb_resid, S.ctrl, 0, -1.0, stream));
+        const hj::Red none{nullptr, nullptr, S.ctrl, 0, 0};
+        for (int64_t k = 0; k < maxc; ++k)
+            HJ_HIP(st.cycle(bufs[k % 3], bufs[(k + 1) % 3], false, -1.0, none));
+        HJ_HIP(st.resid(bufs[maxc % 3], part[1]));
+        HJ_HIP(hj::launch_judge(part[1], st.nb_resid, S.ctrl, maxc, -1.0, stream));
+        if ((r = read_ctrl(S, stream, c)) != HJ_OK) return r;
     } else {
         const double tol = p.rel_tol;
         int64_t next = 0;
@@ -171,40 +191,35 @@ hj_status drive(const Step &st, void *xu, void *xs, const hj_params &p, int64_t 
             const int64_t k = std::min<int64_t>(batch, maxc - next);
             for (int64_t i = 0; i < k; ++i) {
                 const int64_t cc = next + i;
-                HJ_HIP(st.cycle(bufs[cc & 1], bufs[(cc + 1) & 1], true, tol));
+                const hj::Red red{part[cc & 1], part[(cc + 1) & 1], S.ctrl, cc, cc > 0 ? st.nb_cycle : 0};
+                HJ_HIP(st.cycle(bufs[cc % 3], bufs[(cc + 1) % 3], true, tol, red));
             }
             next += k;
             HJ_HIP(hipMemcpyAsync(&S.host[slot], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
             HJ_HIP(hipEventRecord(S.ev[slot], stream));
             return HJ_OK;
         };
-        hj_status r = enqueue(0);
-        if (r != HJ_OK) return r;
+        if ((r = enqueue(0)) != HJ_OK) return r;
         int slot = 0;
         for (;;) {
             const bool more = next < maxc;
-            if (more) {
-                r = enqueue(slot ^ 1);  // keep the GPU fed while this batch is checked
-                if (r != HJ_OK) return r;
-            }
+            if (more && (r = enqueue(slot ^ 1)) != HJ_OK) return r;  // keep the GPU fed
             HJ_HIP(hipEventSynchronize(S.ev[slot]));
             if (S.host[slot].status != hj::ST_RUNNING || !more) break;
             slot ^= 1;
         }
-        HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
-        HJ_HIP(hipStreamSynchronize(stream));
-        c = S.host[0];
+        if ((r = read_ctrl(S, stream, c)) != HJ_OK) return r;
         if (c.status == hj::ST_RUNNING) {
-            // all max_cycles cycles ran; judge the last iterate too
-            HJ_HIP(st.resid(bufs[maxc & 1], maxc, tol));
-            HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
-            HJ_HIP(hipStreamSynchronize(stream));
-            c = S.host[0];
+            // every cycle ran: judge the last two iterates here
+            HJ_HIP(hj::launch_judge(part[(maxc - 1) & 1], st.nb_cycle, S.ctrl, maxc - 1, tol, stream));
+            HJ_HIP(st.resid(bufs[maxc % 3], part[maxc & 1]));
+            HJ_HIP(hj::launch_judge(part[maxc & 1], st.nb_resid, S.ctrl, maxc, tol, stream));
+            if ((r = read_ctrl(S, stream, c)) != HJ_OK) return r;
         }
         final_c = c.status != hj::ST_RUNNING ? c.done_cycle : maxc;
     }
-    if (final_c & 1) {
-        HJ_HIP(st.copy(xu, xs));
+    if (final_c % 3 != 0) {
+        HJ_HIP(st.copy(xu, bufs[final_c % 3]));
         HJ_HIP(hipStreamSynchronize(stream));
     }
     if (info) {
@@ -233,6 +248,7 @@ hj::Geom2 make_geom2(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, c
     g.ntx = hj::axis_count(g.nx, g.tx, g.ox);
     g.nty = hj::axis_count(g.ny, g.ty, g.oy);
     g.iso = hx == hy;
+    g.reg = (p.flags & HJ_FLAG_LDS_KERNEL) ? 0 : 1;
     g.hh = hx * hx;
     g.wx = 1.0 / (hx * hx);
     g.wy = 1.0 / (hy * hy);
@@ -298,24 +314,28 @@ hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, 
     const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
     const size_t es = esize(dtype);
     const bool hier = P.method == HJ_HIERARCHICAL;
-    int64_t npart = hj::resid2d_blocks(g);
-    npart = std::max(npart, hier ? hj::cycle2d_blocks(g) : hj::sweep2d_blocks(g));
-    if ((r = scratch_ensure(S, (size_t)ny * (size_t)ld * es, npart)) != HJ_OK) return r;
+    const int64_t nbc = hier ? hj::cycle2d_blocks(g) : hj::sweep2d_blocks(g);
+    const int64_t nbr = hj::resid2d_blocks(g);
+    if (nbc > INT32_MAX || nbr > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "grid too large");
+    const size_t xbytes = (size_t)ny * (size_t)ld * es;
+    if ((r = scratch_ensure(S, 2 * xbytes, 2 * std::max(nbc, nbr))) != HJ_OK) return r;
     hipStream_t st = (hipStream_t)stream;
 
     Step step;
-    step.cycle = [&](const void *xi, void *xo, bool res, double tol) {
-        return hier ? hj::launch_cycle2d(dt, g, P.s, res, f, xi, xo, S.partials, S.ctrl, tol, st)
-                    : hj::launch_sweep2d(dt, g, res, f, xi, xo, S.partials, S.ctrl, tol, st);
+    step.nb_cycle = (int)nbc;
+    step.nb_resid = (int)nbr;
+    step.cycle = [&](const void *xi, void *xo, bool res, double tol, const hj::Red &red) {
+        return hier ? hj::launch_cycle2d(dt, g, P.s, res, f, xi, xo, red, tol, st)
+                    : hj::launch_sweep2d(dt, g, res, f, xi, xo, red, tol, st);
     };
-    step.resid = [&](const void *xi, int64_t c, double tol) {
-        return hj::launch_resid2d(dt, g, f, xi, nullptr, S.partials, S.ctrl, c, tol, st);
+    step.resid = [&](const void *xi, double *part) {
+        return hj::launch_resid2d(dt, g, f, xi, nullptr, part, st);
     };
     step.copy = [&](void *dst, const void *src) {
         return hipMemcpy2DAsync(dst, (size_t)ld * es, src, (size_t)ld * es, (size_t)nx * es,
                                 (size_t)ny, hipMemcpyDeviceToDevice, st);
     };
-    return drive(step, x, S.xbuf, P, hier ? P.s : 1, st, S, info);
+    return drive(step, x, S.xbuf, xbytes, P, hier ? P.s : 1, st, S, info);
 }
 
 hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *x,
@@ -343,23 +363,27 @@ hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *
     const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
     const size_t es = esize(dtype);
     const bool hier = P.method == HJ_HIERARCHICAL;
-    int64_t npart = hj::resid1d_blocks(g);
-    npart = std::max(npart, hier ? hj::cycle1d_blocks(g) : hj::sweep1d_blocks(g));
-    if ((r = scratch_ensure(S, (size_t)n * es, npart)) != HJ_OK) return r;
+    const int64_t nbc = hier ? hj::cycle1d_blocks(g) : hj::sweep1d_blocks(g);
+    const int64_t nbr = hj::resid1d_blocks(g);
+    if (nbc > INT32_MAX || nbr > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "grid too large");
+    const size_t xbytes = (size_t)n * es;
+    if ((r = scratch_ensure(S, 2 * xbytes, 2 * std::max(nbc, nbr))) != HJ_OK) return r;
     hipStream_t st = (hipStream_t)stream;
 
     Step step;
-    step.cycle = [&](const void *xi, void *xo, bool res, double tol) {
-        return hier ? hj::launch_cycle1d(dt, g, P.s, res, f, xi, xo, S.partials, S.ctrl, tol, st)
-                    : hj::launch_sweep1d(dt, g, res, f, xi, xo, S.partials, S.ctrl, tol, st);
+    step.nb_cycle = (int)nbc;
+    step.nb_resid = (int)nbr;
+    step.cycle = [&](const void *xi, void *xo, bool res, double tol, const hj::Red &red) {
+        return hier ? hj::launch_cycle1d(dt, g, P.s, res, f, xi, xo, red, tol, st)
+                    : hj::launch_sweep1d(dt, g, res, f, xi, xo, red, tol, st);
     };
-    step.resid = [&](const void *xi, int64_t c, double tol) {
-        return hj::launch_resid1d(dt, g, f, xi, nullptr, S.partials, S.ctrl, c, tol, st);
+    step.resid = [&](const void *xi, double *part) {
+        return hj::launch_resid1d(dt, g, f, xi, nullptr, part, st);
     };
     step.copy = [&](void *dst, const void *src) {
         return hipMemcpyAsync(dst, src, (size_t)n * es, hipMemcpyDeviceToDevice, st);
     };
-    return drive(step, x, S.xbuf, P, hier ? P.s : 1, st, S, info);
+    return drive(step, x, S.xbuf, xbytes, P, hier ? P.s : 1, st, S, info);
 }
 
 hj_status hj_residual(int32_t dim, int64_t nx, int64_t ny, int64_t ld, double hx, double hy,
@@ -394,14 +418,20 @@ hj_status hj_residual(int32_t dim, int64_t nx, int64_t ny, int64_t ld, double hx
         hj_params P;
         hj_params_default(&P);
         const hj::Geom2 g = make_geom2(nx, ny, ld, hx, hy, P);
-        if ((r = scratch_ensure(S, 0, hj::resid2d_blocks(g))) != HJ_OK) return r;
+        const int64_t nb = hj::resid2d_blocks(g);
+        if (nb > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "grid too large");
+        if ((r = scratch_ensure(S, 0, 2 * nb)) != HJ_OK) return r;
         HJ_HIP(hj::launch_ctrl_init(S.ctrl, st));
-        HJ_HIP(hj::launch_resid2d(dt, g, f, x, r_out, S.partials, S.ctrl, 0, -1.0, st));
+        HJ_HIP(hj::launch_resid2d(dt, g, f, x, r_out, S.partials, st));
+        HJ_HIP(hj::launch_judge(S.partials, (int)nb, S.ctrl, 0, -1.0, st));
     } else {
         const hj::Geom1 g = make_geom1(nx, hx, nullptr);
-        if ((r = scratch_ensure(S, 0, hj::resid1d_blocks(g))) != HJ_OK) return r;
+        const int64_t nb = hj::resid1d_blocks(g);
+        if (nb > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "grid too large");
+        if ((r = scratch_ensure(S, 0, 2 * nb)) != HJ_OK) return r;
         HJ_HIP(hj::launch_ctrl_init(S.ctrl, st));
-        HJ_HIP(hj::launch_resid1d(dt, g, f, x, r_out, S.partials, S.ctrl, 0, -1.0, st));
+        HJ_HIP(hj::launch_resid1d(dt, g, f, x, r_out, S.partials, st));
+        HJ_HIP(hj::launch_judge(S.partials, (int)nb, S.ctrl, 0, -1.0, st));
     }
     HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, st));
     HJ_HIP(hipStreamSynchronize(st));

@@ -1,6 +1,6 @@
 // hj_device.h -- device-side building blocks shared by the HIP kernels:
 // the control block of a solve, the tile partition, the XCD-aware block
-// mapping and the deterministic grid-wide FP64 sum.
+// mapping and the deterministic FP64 residual reduction.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,16 +8,16 @@
 
 namespace hj {
 
-// Device-resident state of one solve.  The residual of the iterate a cycle
-// kernel reads is reduced inside that kernel; its last workgroup to finish
-// updates this block, so the host only polls it now and then.
+// Device-resident state of one solve.  Cycle kernels reduce the residual of
+// the iterate they read and judge it on the device (see Red below), so the
+// host only polls this block now and then.
 struct Ctrl {
     double r0sq;         // ||r_0||^2
-    double last_rsq;     // ||r_c||^2 of the latest evaluated iterate
-    int64_t iter;        // index of the iterate the next cycle kernel reads
+    double last_rsq;     // ||r_c||^2 of the latest judged iterate
+    int64_t iter;        // one past the latest judged iterate
     int64_t done_cycle;  // first c that met the tolerance (or went non-finite); -1 otherwise
     int32_t status;      // 0 running, 1 converged, 2 non-finite
-    uint32_t arrive;     // workgroups of the current kernel that have posted a partial
+    int32_t pad;
 };
 
 enum : int32_t { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NONFINITE = 2 };
@@ -93,50 +93,81 @@ __device__ inline double block_sum(double v, double *red /* NT/64 doubles of LDS
     return t;  // identical in every thread
 }
 
-// Decide convergence for iterate c from its squared residual norm.
+// Decide convergence for iterate c from its squared residual norm.  Once a
+// verdict stands the block is frozen, so last_rsq stays that of done_cycle.
 __device__ inline void judge(Ctrl *ctrl, int64_t c, double rsq, double tol)
 {
+    if (ctrl->status != ST_RUNNING) return;
     if (c == 0) ctrl->r0sq = rsq;
     const double r0sq = ctrl->r0sq;
     ctrl->last_rsq = rsq;
-    const double rel = r0sq > 0.0 ? sqrt(rsq) / sqrt(r0sq) : 0.0;
-    if (ctrl->status == ST_RUNNING) {
-        if (!isfinite(rsq)) {
-            ctrl->status = ST_NONFINITE;
-            ctrl->done_cycle = c;
-        } else if (rel <= tol) {
-            ctrl->status = ST_CONVERGED;
-            ctrl->done_cycle = c;
-        }
-    }
     ctrl->iter = c + 1;
+    const double rel = r0sq > 0.0 ? sqrt(rsq) / sqrt(r0sq) : 0.0;
+    int32_t st = ST_RUNNING;
+    if (!isfinite(rsq)) st = ST_NONFINITE;
+    else if (rel <= tol) st = ST_CONVERGED;
+    if (st != ST_RUNNING) {
+        ctrl->done_cycle = c;
+        __hip_atomic_store(&ctrl->status, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
-// Every workgroup posts its partial sum of squares; the last one to arrive
-// adds the partials in index order and judges iterate c (c < 0: ctrl->iter).
+__device__ inline int32_t read_status(const Ctrl *ctrl)
+{
+    return __hip_atomic_load(&ctrl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Residual bookkeeping handed to every kernel that reduces ||r||^2.
+// Each workgroup stores its partial sum in part_cur[blockIdx.x] with a plain
+// store.  The sum over the grid is formed by workgroup 0 of the NEXT kernel on
+// the stream (the kernel boundary makes the partials visible), which judges
+// iterate c - 1; no atomics and no cache-flushing fences inside the grid.
+struct Red {
+    double *part_cur;         // this kernel's partials (one per workgroup)
+    const double *part_prev;  // the previous kernel's partials
+    Ctrl *ctrl;
+    int64_t c;                // index of the iterate this kernel evaluates
+    int nb_prev;              // workgroups of the previous kernel (0: nothing to judge)
+};
+
+// Sum n partials in a fixed order and judge iterate c (one workgroup).
+// Thread t adds chunks of 8 consecutive partials; 4 chunks (32 loads) are in
+// flight per thread before any add, so a 64-lane workgroup reads 16K partials
+// in a few memory latencies instead of one latency per partial.
 template <int NT>
-__device__ inline void grid_finalize(double mine, double *partials, Ctrl *ctrl, int64_t c,
-                                     double tol)
+__device__ inline void judge_partials(const double *part, int n, Ctrl *ctrl, int64_t c, double tol)
 {
     __shared__ double red[NT / 64];
-    __shared__ int last;
-    const double bs = block_sum<NT>(mine, red);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = bs;
-        const unsigned prev = __hip_atomic_fetch_add(&ctrl->arrive, 1u, __ATOMIC_ACQ_REL,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    constexpr int V = 8, U = 4;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += NT) acc += partials[i];
-    const double tot = block_sum<NT>(acc, red);
-    if (threadIdx.x == 0) {
-        judge(ctrl, c < 0 ? ctrl->iter : c, tot, tol);
-        ctrl->arrive = 0u;
+    for (int base = 0; base < n; base += NT * V * U) {
+        double v[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i0 = base + (u * NT + (int)threadIdx.x) * V;
+            if (i0 + V <= n) {
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[u][e] = part[i0 + e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[u][e] = i0 + e < n ? part[i0 + e] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc += v[u][e];
     }
+    const double tot = block_sum<NT>(acc, red);
+    if (threadIdx.x == 0) judge(ctrl, c, tot, tol);
+}
+
+template <int NT>
+__device__ inline void post_partial(double mine, double *part_cur)
+{
+    __shared__ double red[NT / 64];
+    const double bs = block_sum<NT>(mine, red);
+    if (threadIdx.x == 0) part_cur[blockIdx.x] = bs;
 }
 
 }  // namespace hj

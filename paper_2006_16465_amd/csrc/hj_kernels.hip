@@ -13,6 +13,8 @@
 // result and must not be fused.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "hj_launch.h"
 
 namespace hj {
@@ -56,11 +58,14 @@ constexpr int kNT = 256;  // threads per workgroup of every kernel here
 template <typename T, int TX, int TY, bool RES, bool ISO>
 __global__ __launch_bounds__(kNT) void k_cycle2d(Geom2 g, const T *__restrict__ f,
                                                  const T *__restrict__ xin, T *__restrict__ xout,
-                                                 int s, double *__restrict__ partials, Ctrl *ctrl,
-                                                 double tol)
+                                                 int s, Red red, double tol)
 {
     static_assert(kNT % TX == 0 && (TX * TY) % kNT == 0, "tile/threads mismatch");
-    if (RES && ctrl->status != ST_RUNNING) return;
+    if (RES) {
+        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (blockIdx.x == 0 && red.nb_prev > 0)
+            judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
+    }
 
     constexpr int P = TX + 2;          // LDS row pitch, halo column each side
     constexpr int R = TY + 2;          // LDS rows, halo row each side
@@ -148,7 +153,183 @@ __global__ __launch_bounds__(kNT) void k_cycle2d(Geom2 g, const T *__restrict__ 
         if (col_own && r >= rlo && r < rhi) xout[(int64_t)(r0 + r) * ld + c0 + tc] = val[j];
     }
 
-    if (RES) grid_finalize<kNT>(rsq, partials, ctrl, -1, tol);
+    if (RES) post_partial<kNT>(rsq, red.part_cur);
+}
+
+// ============================================================================
+// 2D hierarchical cycle, register-resident.  One wavefront per full tile of
+// TX = 16*C columns by TY = 4*R rows: lane 16k + j holds rows [kR, kR + R) x
+// columns [jC, jC + C) of the tile in VGPRs, so a 16-lane DPP row spans the
+// whole tile width.  x-neighbours in other lanes come from DPP row shifts;
+// y-neighbours in other row groups through four LDS interface rows.  The
+// frozen halo sits in registers (columns -1 and TX, in the first / last lane
+// of each DPP row) and in LDS (rows -1 and TY).  Used when the grid holds at
+// least one full tile in each direction.
+// ============================================================================
+constexpr int kDppRowShr1 = 0x111;  // lane i <- lane i - 1 of its 16-lane row
+constexpr int kDppRowShl1 = 0x101;  // lane i <- lane i + 1 of its 16-lane row
+
+// Lanes whose source falls outside the 16-lane row receive 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+
+// update from the already-summed pairs we = W + E and sn = S + N
+template <typename T, bool ISO>
+__device__ __forceinline__ T upd2_sum(T b, T we, T sn, T wx, T wy, T dinv)
+{
+    if (ISO) return (b + (we + sn)) * T(0.25);
+    return (b + (wx * we + wy * sn)) * dinv;
+}
+
+template <typename T, int C, int R, bool RES, bool ISO>
+__global__ __launch_bounds__(64) void k_cycle2d_reg(Geom2 g, const T *__restrict__ f,
+                                                    const T *__restrict__ xin,
+                                                    T *__restrict__ xout, int nsub, Red red,
+                                                    double tol)
+{
+    constexpr int TX = 16 * C, TY = 4 * R;
+    if (RES) {
+        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (blockIdx.x == 0 && red.nb_prev > 0)
+            judge_partials<64>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
+    }
+    __shared__ T s_top[4][TX];   // first row of each row group (current sweep)
+    __shared__ T s_bot[4][TX];   // last row of each row group
+    __shared__ T s_halo[2][TX];  // frozen rows -1 and TY
+
+    const int lane = threadIdx.x, k = lane >> 4, j = lane & 15;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int bi = tile / g.ntx, bj = tile - bi * g.ntx;
+    const int r0 = axis_origin(g.ny, TY, g.oy, bi);
+    const int c0 = axis_origin(g.nx, TX, g.ox, bj);
+    const int64_t ld = g.ld;
+    const int lr0 = k * R, lc0 = j * C;
+    const int64_t base = (int64_t)(r0 + lr0) * ld + c0 + lc0;
+
+    // step 1: tile, halo and f into registers / LDS
+    T x[R][C], bh[R][C], hw[R], he[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            x[i][c] = xin[base + (int64_t)i * ld + c];
+            bh[i][c] = f[base + (int64_t)i * ld + c];  // f for now, h^2 f after the residual
+        }
+        hw[i] = (j == 0 && c0 > 0) ? xin[base + (int64_t)i * ld - 1] : T(0);
+        he[i] = (j == 15 && c0 + TX < g.nx) ? xin[base + (int64_t)i * ld + C] : T(0);
+    }
+    if (k == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            s_halo[0][lc0 + c] = r0 > 0 ? xin[(int64_t)(r0 - 1) * ld + c0 + lc0 + c] : T(0);
+    }
+    if (k == 3) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            s_halo[1][lc0 + c] =
+                r0 + TY < g.ny ? xin[(int64_t)(r0 + TY) * ld + c0 + lc0 + c] : T(0);
+    }
+    const int rlo = axis_own_begin(g.ny, TY, g.oy, bi) - r0 - lr0;
+    const int rhi = axis_own_end(g.ny, TY, g.oy, bi, g.nty) - r0 - lr0;
+    const int clo = axis_own_begin(g.nx, TX, g.ox, bj) - c0 - lc0;
+    const int chi = axis_own_end(g.nx, TX, g.ox, bj, g.ntx) - c0 - lc0;
+
+    const T wx = T(g.wx), wy = T(g.wy), dinv = T(g.dinv);
+    T up[C], dn[C];
+    auto exchange = [&]() {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s_top[k][lc0 + c] = x[0][c];
+            s_bot[k][lc0 + c] = x[R - 1][c];
+        }
+        __syncthreads();
+        const T *pu = k == 0 ? &s_halo[0][lc0] : &s_bot[k - 1][lc0];
+        const T *pd = k == 3 ? &s_halo[1][lc0] : &s_top[k + 1][lc0];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            up[c] = pu[c];
+            dn[c] = pd[c];
+        }
+        __syncthreads();  // every lane has read before the next exchange writes
+    };
+
+    // One sub-iteration over the lane's rows, top to bottom, in place: prev
+    // keeps the old row above.  FIRST: bh still holds f; it also accumulates
+    // the residual of the incoming iterate over the owned points and turns f
+    // into h^2 f (iso) as it goes.
+    double rsq = 0.0;
+    const T hh = T(g.hh);
+    auto sweep = [&](auto first_tag) {
+        constexpr bool FIRST = decltype(first_tag)::value;
+        T prev[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) prev[c] = up[c];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const T wl = dpp_shift<kDppRowShr1>(x[i][C - 1]);
+            const T er = dpp_shift<kDppRowShl1>(x[i][0]);
+            T nw[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T w = c > 0 ? x[i][c - 1] : wl;
+                const T e = c < C - 1 ? x[i][c + 1] : er;
+                T we = w + e;
+                // the halo registers are 0 except in the first / last lane of a
+                // DPP row, where the shifted value is 0: the sum stays W + E
+                if (c == 0) we = we + hw[i];
+                if (c == C - 1) we = we + he[i];
+                const T below = i < R - 1 ? x[i + 1][c] : dn[c];
+                T b = bh[i][c];
+                if (FIRST) {
+                    if (RES && i >= rlo && i < rhi && c >= clo && c < chi) {
+                        const double wa = c > 0 ? (double)w : (double)wl + (double)hw[i];
+                        const double ea = c < C - 1 ? (double)e : (double)er + (double)he[i];
+                        const double rr = res2((double)b, (double)x[i][c], wa, ea, (double)prev[c],
+                                               (double)below, g.wx, g.wy);
+                        rsq += rr * rr;
+                    }
+                    if (ISO) b = hh * b;
+                    bh[i][c] = b;
+                }
+                nw[c] = upd2_sum<T, ISO>(b, we, prev[c] + below, wx, wy, dinv);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                prev[c] = x[i][c];
+                x[i][c] = nw[c];
+            }
+        }
+    };
+
+    // step 2: nsub sub-iterations with the halo frozen
+    exchange();
+    sweep(std::true_type{});
+    for (int it = 1; it < nsub; ++it) {
+        exchange();
+        sweep(std::false_type{});
+    }
+
+    // step 3: owned points back to global memory
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (i >= rlo && i < rhi && c >= clo && c < chi) xout[base + (int64_t)i * ld + c] = x[i][c];
+
+    if (RES) post_partial<64>(rsq, red.part_cur);
 }
 
 // ============================================================================
@@ -161,10 +342,13 @@ constexpr int kSBX = 64, kSBY = 4, kSRPT = 8;
 template <typename T, bool RES, bool ISO, bool SWEEP>
 __global__ __launch_bounds__(kNT) void k_sweep2d(Geom2 g, const T *__restrict__ f,
                                                  const T *__restrict__ xin, T *__restrict__ xout,
-                                                 double *__restrict__ partials, Ctrl *ctrl,
-                                                 int64_t c_eval, double tol)
+                                                 Red red, double tol)
 {
-    if (SWEEP && RES && ctrl->status != ST_RUNNING) return;
+    if (SWEEP && RES) {
+        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (blockIdx.x == 0 && red.nb_prev > 0)
+            judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
+    }
     const int gx = (g.nx + kSBX - 1) / kSBX;
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int by = b / gx, bx = b - by * gx;
@@ -197,7 +381,7 @@ __global__ __launch_bounds__(kNT) void k_sweep2d(Geom2 g, const T *__restrict__ 
             }
         }
     }
-    if (RES) grid_finalize<kNT>(rsq, partials, ctrl, c_eval, tol);
+    if (RES) post_partial<kNT>(rsq, red.part_cur);
 }
 
 // ============================================================================
@@ -207,10 +391,13 @@ __global__ __launch_bounds__(kNT) void k_sweep2d(Geom2 g, const T *__restrict__ 
 template <typename T, int TT, bool RES>
 __global__ __launch_bounds__(kNT) void k_cycle1d(Geom1 g, const T *__restrict__ f,
                                                  const T *__restrict__ xin, T *__restrict__ xout,
-                                                 int s, double *__restrict__ partials, Ctrl *ctrl,
-                                                 double tol)
+                                                 int s, Red red, double tol)
 {
-    if (RES && ctrl->status != ST_RUNNING) return;
+    if (RES) {
+        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (blockIdx.x == 0 && red.nb_prev > 0)
+            judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
+    }
     constexpr int G = TT <= kNT ? kNT / TT : 1;
     constexpr int PER = TT <= kNT ? 1 : TT / kNT;
     constexpr int P = TT + 2;
@@ -290,17 +477,20 @@ __global__ __launch_bounds__(kNT) void k_cycle1d(Geom1 g, const T *__restrict__ 
         if (live && lc >= lo && lc < hi) xout[x0 + lc] = val[j];
     }
 
-    if (RES) grid_finalize<kNT>(rsq, partials, ctrl, -1, tol);
+    if (RES) post_partial<kNT>(rsq, red.part_cur);
 }
 
 // 1D classical sweep / residual: one point per thread.
 template <typename T, bool RES, bool SWEEP>
 __global__ __launch_bounds__(kNT) void k_sweep1d(Geom1 g, const T *__restrict__ f,
                                                  const T *__restrict__ xin, T *__restrict__ xout,
-                                                 double *__restrict__ partials, Ctrl *ctrl,
-                                                 int64_t c_eval, double tol)
+                                                 Red red, double tol)
 {
-    if (SWEEP && RES && ctrl->status != ST_RUNNING) return;
+    if (SWEEP && RES) {
+        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (blockIdx.x == 0 && red.nb_prev > 0)
+            judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
+    }
     const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * kNT + threadIdx.x;
     double rsq = 0.0;
     if (i < g.n) {
@@ -314,7 +504,7 @@ __global__ __launch_bounds__(kNT) void k_sweep1d(Geom1 g, const T *__restrict__ 
             rsq += rr * rr;
         }
     }
-    if (RES) grid_finalize<kNT>(rsq, partials, ctrl, c_eval, tol);
+    if (RES) post_partial<kNT>(rsq, red.part_cur);
 }
 
 __global__ void k_ctrl_init(Ctrl *ctrl)
@@ -324,34 +514,64 @@ __global__ void k_ctrl_init(Ctrl *ctrl)
     ctrl->iter = 0;
     ctrl->done_cycle = -1;
     ctrl->status = ST_RUNNING;
-    ctrl->arrive = 0u;
+    ctrl->pad = 0;
+}
+
+// Judge iterate c from n partials left by the previous kernel (one workgroup).
+__global__ __launch_bounds__(kNT) void k_judge(const double *part, int n, Ctrl *ctrl, int64_t c,
+                                               double tol)
+{
+    judge_partials<kNT>(part, n, ctrl, c, tol);
 }
 
 // ---------------------------------------------------------------- dispatch
-template <typename T, int TX, int TY>
-hipError_t cyc2(const Geom2 &g, int s, bool res, const void *f, const void *xin, void *xout,
-                double *part, Ctrl *ctrl, double tol, hipStream_t st)
+template <typename T, int C, int R>
+hipError_t cyc2_reg(const Geom2 &g, int s, bool res, const void *f, const void *xin, void *xout,
+                    const Red &red, double tol, hipStream_t st)
 {
     const unsigned nb = (unsigned)((int64_t)g.ntx * g.nty);
     const T *F = (const T *)f;
     const T *XI = (const T *)xin;
     T *XO = (T *)xout;
     if (res) {
-        if (g.iso) k_cycle2d<T, TX, TY, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, part, ctrl, tol);
-        else k_cycle2d<T, TX, TY, true, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, part, ctrl, tol);
+        if (g.iso) k_cycle2d_reg<T, C, R, true, true><<<nb, 64, 0, st>>>(g, F, XI, XO, s, red, tol);
+        else k_cycle2d_reg<T, C, R, true, false><<<nb, 64, 0, st>>>(g, F, XI, XO, s, red, tol);
     } else {
-        if (g.iso) k_cycle2d<T, TX, TY, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, part, ctrl, tol);
-        else k_cycle2d<T, TX, TY, false, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, part, ctrl, tol);
+        if (g.iso) k_cycle2d_reg<T, C, R, false, true><<<nb, 64, 0, st>>>(g, F, XI, XO, s, red, tol);
+        else k_cycle2d_reg<T, C, R, false, false><<<nb, 64, 0, st>>>(g, F, XI, XO, s, red, tol);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int TX, int TY>
+hipError_t cyc2(const Geom2 &g, int s, bool res, const void *f, const void *xin, void *xout,
+                const Red &red, double tol, hipStream_t st)
+{
+    // full tiles of a register-resident shape: one wavefront per tile
+    if (g.reg && g.nx >= TX && g.ny >= TY) {
+        if constexpr ((TX == 32 || TX == 64) && (TY == 16 || TY == 32))
+            return cyc2_reg<T, TX / 16, TY / 4>(g, s, res, f, xin, xout, red, tol, st);
+    }
+    const unsigned nb = (unsigned)((int64_t)g.ntx * g.nty);
+    const T *F = (const T *)f;
+    const T *XI = (const T *)xin;
+    T *XO = (T *)xout;
+    if (res) {
+        if (g.iso) k_cycle2d<T, TX, TY, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
+        else k_cycle2d<T, TX, TY, true, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
+    } else {
+        if (g.iso) k_cycle2d<T, TX, TY, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
+        else k_cycle2d<T, TX, TY, false, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
     }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t cyc2_t(const Geom2 &g, int s, bool res, const void *f, const void *xin, void *xout,
-                  double *part, Ctrl *ctrl, double tol, hipStream_t st)
+                  const Red &red, double tol, hipStream_t st)
 {
 #define HJ_TILE(a, b)                                                                     \
-    if (g.tx == a && g.ty == b) return cyc2<T, a, b>(g, s, res, f, xin, xout, part, ctrl, tol, st);
+    if (g.tx == a && g.ty == b) return cyc2<T, a, b>(g, s, res, f, xin, xout, red, tol, st);
     HJ_TILE(16, 16) HJ_TILE(16, 32) HJ_TILE(16, 64)
     HJ_TILE(32, 16) HJ_TILE(32, 32) HJ_TILE(32, 64)
     HJ_TILE(64, 16) HJ_TILE(64, 32) HJ_TILE(64, 64)
@@ -361,26 +581,26 @@ hipError_t cyc2_t(const Geom2 &g, int s, bool res, const void *f, const void *xi
 
 template <typename T, int TT>
 hipError_t cyc1(const Geom1 &g, int s, bool res, const void *f, const void *xin, void *xout,
-                double *part, Ctrl *ctrl, double tol, hipStream_t st)
+                const Red &red, double tol, hipStream_t st)
 {
     constexpr int G = TT <= kNT ? kNT / TT : 1;
     const unsigned nb = (unsigned)((g.nt + G - 1) / G);
-    if (res) k_cycle1d<T, TT, true><<<nb, kNT, 0, st>>>(g, (const T *)f, (const T *)xin, (T *)xout, s, part, ctrl, tol);
-    else k_cycle1d<T, TT, false><<<nb, kNT, 0, st>>>(g, (const T *)f, (const T *)xin, (T *)xout, s, part, ctrl, tol);
+    if (res) k_cycle1d<T, TT, true><<<nb, kNT, 0, st>>>(g, (const T *)f, (const T *)xin, (T *)xout, s, red, tol);
+    else k_cycle1d<T, TT, false><<<nb, kNT, 0, st>>>(g, (const T *)f, (const T *)xin, (T *)xout, s, red, tol);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t cyc1_t(const Geom1 &g, int s, bool res, const void *f, const void *xin, void *xout,
-                  double *part, Ctrl *ctrl, double tol, hipStream_t st)
+                  const Red &red, double tol, hipStream_t st)
 {
     switch (g.t) {
-    case 32: return cyc1<T, 32>(g, s, res, f, xin, xout, part, ctrl, tol, st);
-    case 64: return cyc1<T, 64>(g, s, res, f, xin, xout, part, ctrl, tol, st);
-    case 128: return cyc1<T, 128>(g, s, res, f, xin, xout, part, ctrl, tol, st);
-    case 256: return cyc1<T, 256>(g, s, res, f, xin, xout, part, ctrl, tol, st);
-    case 512: return cyc1<T, 512>(g, s, res, f, xin, xout, part, ctrl, tol, st);
-    case 1024: return cyc1<T, 1024>(g, s, res, f, xin, xout, part, ctrl, tol, st);
+    case 32: return cyc1<T, 32>(g, s, res, f, xin, xout, red, tol, st);
+    case 64: return cyc1<T, 64>(g, s, res, f, xin, xout, red, tol, st);
+    case 128: return cyc1<T, 128>(g, s, res, f, xin, xout, red, tol, st);
+    case 256: return cyc1<T, 256>(g, s, res, f, xin, xout, red, tol, st);
+    case 512: return cyc1<T, 512>(g, s, res, f, xin, xout, red, tol, st);
+    case 1024: return cyc1<T, 1024>(g, s, res, f, xin, xout, red, tol, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -419,79 +639,87 @@ int64_t sweep1d_blocks(const Geom1 &g) { return (g.n + kNT - 1) / kNT; }
 int64_t resid1d_blocks(const Geom1 &g) { return sweep1d_blocks(g); }
 
 hipError_t launch_cycle2d(int dt, const Geom2 &g, int s, bool res, const void *f, const void *xin,
-                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st)
+                          void *xout, const Red &red, double tol, hipStream_t st)
 {
-    if (dt == F64) return cyc2_t<double>(g, s, res, f, xin, xout, partials, ctrl, tol, st);
-    return cyc2_t<float>(g, s, res, f, xin, xout, partials, ctrl, tol, st);
+    if (dt == F64) return cyc2_t<double>(g, s, res, f, xin, xout, red, tol, st);
+    return cyc2_t<float>(g, s, res, f, xin, xout, red, tol, st);
 }
 
 template <typename T>
 static hipError_t sw2(const Geom2 &g, bool res, const void *f, const void *xin, void *xout,
-                      double *part, Ctrl *ctrl, double tol, hipStream_t st)
+                      const Red &red, double tol, hipStream_t st)
 {
     const unsigned nb = (unsigned)sweep2d_blocks(g);
     const T *F = (const T *)f;
     const T *XI = (const T *)xin;
     T *XO = (T *)xout;
     if (res) {
-        if (g.iso) k_sweep2d<T, true, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, part, ctrl, -1, tol);
-        else k_sweep2d<T, true, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, part, ctrl, -1, tol);
+        if (g.iso) k_sweep2d<T, true, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, red, tol);
+        else k_sweep2d<T, true, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, red, tol);
     } else {
-        if (g.iso) k_sweep2d<T, false, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, part, ctrl, -1, tol);
-        else k_sweep2d<T, false, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, part, ctrl, -1, tol);
+        if (g.iso) k_sweep2d<T, false, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, red, tol);
+        else k_sweep2d<T, false, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, red, tol);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_sweep2d(int dt, const Geom2 &g, bool res, const void *f, const void *xin,
-                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st)
+                          void *xout, const Red &red, double tol, hipStream_t st)
 {
-    if (dt == F64) return sw2<double>(g, res, f, xin, xout, partials, ctrl, tol, st);
-    return sw2<float>(g, res, f, xin, xout, partials, ctrl, tol, st);
+    if (dt == F64) return sw2<double>(g, res, f, xin, xout, red, tol, st);
+    return sw2<float>(g, res, f, xin, xout, red, tol, st);
 }
 
 hipError_t launch_resid2d(int dt, const Geom2 &g, const void *f, const void *x, void *r_out,
-                          double *partials, Ctrl *ctrl, int64_t c, double tol, hipStream_t st)
+                          double *part, hipStream_t st)
 {
     const unsigned nb = (unsigned)sweep2d_blocks(g);
+    const Red red{part, nullptr, nullptr, 0, 0};
     if (dt == F64)
         k_sweep2d<double, true, true, false><<<nb, kNT, 0, st>>>(
-            g, (const double *)f, (const double *)x, (double *)r_out, partials, ctrl, c, tol);
+            g, (const double *)f, (const double *)x, (double *)r_out, red, -1.0);
     else
         k_sweep2d<float, true, true, false><<<nb, kNT, 0, st>>>(
-            g, (const float *)f, (const float *)x, (float *)r_out, partials, ctrl, c, tol);
+            g, (const float *)f, (const float *)x, (float *)r_out, red, -1.0);
     return hipGetLastError();
 }
 
 hipError_t launch_cycle1d(int dt, const Geom1 &g, int s, bool res, const void *f, const void *xin,
-                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st)
+                          void *xout, const Red &red, double tol, hipStream_t st)
 {
-    if (dt == F64) return cyc1_t<double>(g, s, res, f, xin, xout, partials, ctrl, tol, st);
-    return cyc1_t<float>(g, s, res, f, xin, xout, partials, ctrl, tol, st);
+    if (dt == F64) return cyc1_t<double>(g, s, res, f, xin, xout, red, tol, st);
+    return cyc1_t<float>(g, s, res, f, xin, xout, red, tol, st);
 }
 
 hipError_t launch_sweep1d(int dt, const Geom1 &g, bool res, const void *f, const void *xin,
-                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st)
+                          void *xout, const Red &red, double tol, hipStream_t st)
 {
     const unsigned nb = (unsigned)sweep1d_blocks(g);
     if (dt == F64) {
-        if (res) k_sweep1d<double, true, true><<<nb, kNT, 0, st>>>(g, (const double *)f, (const double *)xin, (double *)xout, partials, ctrl, -1, tol);
-        else k_sweep1d<double, false, true><<<nb, kNT, 0, st>>>(g, (const double *)f, (const double *)xin, (double *)xout, partials, ctrl, -1, tol);
+        if (res) k_sweep1d<double, true, true><<<nb, kNT, 0, st>>>(g, (const double *)f, (const double *)xin, (double *)xout, red, tol);
+        else k_sweep1d<double, false, true><<<nb, kNT, 0, st>>>(g, (const double *)f, (const double *)xin, (double *)xout, red, tol);
     } else {
-        if (res) k_sweep1d<float, true, true><<<nb, kNT, 0, st>>>(g, (const float *)f, (const float *)xin, (float *)xout, partials, ctrl, -1, tol);
-        else k_sweep1d<float, false, true><<<nb, kNT, 0, st>>>(g, (const float *)f, (const float *)xin, (float *)xout, partials, ctrl, -1, tol);
+        if (res) k_sweep1d<float, true, true><<<nb, kNT, 0, st>>>(g, (const float *)f, (const float *)xin, (float *)xout, red, tol);
+        else k_sweep1d<float, false, true><<<nb, kNT, 0, st>>>(g, (const float *)f, (const float *)xin, (float *)xout, red, tol);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_resid1d(int dt, const Geom1 &g, const void *f, const void *x, void *r_out,
-                          double *partials, Ctrl *ctrl, int64_t c, double tol, hipStream_t st)
+                          double *part, hipStream_t st)
 {
     const unsigned nb = (unsigned)sweep1d_blocks(g);
+    const Red red{part, nullptr, nullptr, 0, 0};
     if (dt == F64)
-        k_sweep1d<double, true, false><<<nb, kNT, 0, st>>>(g, (const double *)f, (const double *)x, (double *)r_out, partials, ctrl, c, tol);
+        k_sweep1d<double, true, false><<<nb, kNT, 0, st>>>(g, (const double *)f, (const double *)x, (double *)r_out, red, -1.0);
     else
-        k_sweep1d<float, true, false><<<nb, kNT, 0, st>>>(g, (const float *)f, (const float *)x, (float *)r_out, partials, ctrl, c, tol);
+        k_sweep1d<float, true, false><<<nb, kNT, 0, st>>>(g, (const float *)f, (const float *)x, (float *)r_out, red, -1.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_judge(const double *part, int n, Ctrl *ctrl, int64_t c, double tol, hipStream_t st)
+{
+    k_judge<<<1, kNT, 0, st>>>(part, n, ctrl, c, tol);
     return hipGetLastError();
 }
 

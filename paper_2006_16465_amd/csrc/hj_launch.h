@@ -17,6 +17,7 @@ struct Geom2 {
     int tx, ty, ox, oy;  // tile extents and overlaps
     int ntx, nty;        // tiles per axis
     int iso;             // hx == hy: use the h^2 f form of the update
+    int reg;             // allow the register-resident cycle kernel (full tiles only)
     double hh;           // h^2 (iso)
     double wx, wy, dinv; // 1/hx^2, 1/hy^2, 1/(2wx + 2wy)
 };
@@ -40,23 +41,27 @@ int64_t cycle1d_blocks(const Geom1 &g);
 int64_t sweep1d_blocks(const Geom1 &g);
 int64_t resid1d_blocks(const Geom1 &g);
 
-// One hierarchical cycle xin -> xout.  res: also reduce ||f - A xin||^2 and
-// judge iterate ctrl->iter against tol (skipped entirely once ctrl->status is set).
+// One hierarchical cycle xin -> xout.  res: also reduce ||f - A xin||^2 into
+// red.part_cur, judge iterate red.c - 1 from red.part_prev (workgroup 0), and
+// skip all work once red.ctrl->status is set.
 hipError_t launch_cycle2d(int dt, const Geom2 &g, int s, bool res, const void *f, const void *xin,
-                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st);
+                          void *xout, const Red &red, double tol, hipStream_t st);
 // One classical sweep over the whole grid, same residual contract.
 hipError_t launch_sweep2d(int dt, const Geom2 &g, bool res, const void *f, const void *xin,
-                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st);
-// Residual of x (optionally stored to r_out), judged as iterate c.
+                          void *xout, const Red &red, double tol, hipStream_t st);
+// Residual of x (optionally stored to r_out); partial sums of ||r||^2 into part.
 hipError_t launch_resid2d(int dt, const Geom2 &g, const void *f, const void *x, void *r_out,
-                          double *partials, Ctrl *ctrl, int64_t c, double tol, hipStream_t st);
+                          double *part, hipStream_t st);
 
 hipError_t launch_cycle1d(int dt, const Geom1 &g, int s, bool res, const void *f, const void *xin,
-                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st);
+                          void *xout, const Red &red, double tol, hipStream_t st);
 hipError_t launch_sweep1d(int dt, const Geom1 &g, bool res, const void *f, const void *xin,
-                          void *xout, double *partials, Ctrl *ctrl, double tol, hipStream_t st);
+                          void *xout, const Red &red, double tol, hipStream_t st);
 hipError_t launch_resid1d(int dt, const Geom1 &g, const void *f, const void *x, void *r_out,
-                          double *partials, Ctrl *ctrl, int64_t c, double tol, hipStream_t st);
+                          double *part, hipStream_t st);
+
+// Sum n partials and judge iterate c (one workgroup).
+hipError_t launch_judge(const double *part, int n, Ctrl *ctrl, int64_t c, double tol, hipStream_t st);
 
 hipError_t launch_ctrl_init(Ctrl *ctrl, hipStream_t st);
 

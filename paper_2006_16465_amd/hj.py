@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_PKG, "libhj.so")
 HJ_OK, HJ_ERR_INVALID_ARG, HJ_ERR_NOT_CONVERGED, HJ_ERR_NONFINITE, HJ_ERR_UNSUPPORTED, HJ_ERR_HIP = range(6)
 HJ_F64, HJ_F32 = 0, 1
 HJ_HIERARCHICAL, HJ_GLOBAL = 0, 1
+HJ_FLAG_LDS_KERNEL = 0x1
 METHODS = {"hierarchical": HJ_HIERARCHICAL, "global": HJ_GLOBAL}
 
 
@@ -114,7 +115,7 @@ def axis_tiles(n: int, tile: int, overlap: int = 0) -> int:
 
 
 def make_params(tile=32, s=16, method="hierarchical", rel_tol=1e-6, max_cycles=1_000_000,
-                check_every=32, overlap=0) -> Params:
+                check_every=32, overlap=0, lds_kernel=False) -> Params:
     p = Params()
     load().hj_params_default(ctypes.byref(p))
     tx, ty = (tile, tile) if isinstance(tile, int) else tile
@@ -125,6 +126,7 @@ def make_params(tile=32, s=16, method="hierarchical", rel_tol=1e-6, max_cycles=1
     p.rel_tol = rel_tol
     p.max_cycles = max_cycles
     p.check_every = check_every
+    p.flags = HJ_FLAG_LDS_KERNEL if lds_kernel else 0
     return p
 
 
@@ -178,8 +180,9 @@ def solve_1d(f, x, h, *, tile=32, s=16, method="hierarchical", rel_tol=1e-6, max
 
 def solve_2d(f, x, h=None, *, hx=None, hy=None, tile=(32, 32), s=16, method="hierarchical",
              rel_tol=1e-6, max_cycles=1_000_000, check_every=32, overlap=(0, 0),
-             allow_not_converged=False) -> Info:
-    """Solve the 5-point Poisson system in place in x, f and x of shape (ny, nx) (hj_solve_2d)."""
+             allow_not_converged=False, lds_kernel=False) -> Info:
+    """Solve the 5-point Poisson system in place in x, f and x of shape (ny, nx) (hj_solve_2d).
+    lds_kernel=True forces the LDS ping-pong cycle kernel (same iterates)."""
     _check_pair(f, x)
     hx = hx if hx is not None else h
     hy = hy if hy is not None else hx
@@ -187,7 +190,7 @@ def solve_2d(f, x, h=None, *, hx=None, hy=None, tile=(32, 32), s=16, method="hie
     if _ld(x) != ld:
         raise ValueError("f and x must share the row stride")
     ny, nx = f.shape
-    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap)
+    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap, lds_kernel)
     info = _Info()
     with _device(f):
         st = load().hj_solve_2d(nx, ny, ld, float(hx), float(hy), _dtype_code(f), f.data_ptr(),

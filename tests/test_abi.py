@@ -55,7 +55,7 @@ FAKE = 0x10000  # aligned non-NULL pointer; validation must reject before it is 
     ((8, 8, 8, 0.1, 0.1, 0), {"overlap_x": 32}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"overlap_y": -2}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"method": 5}, hj.HJ_ERR_INVALID_ARG),
-    ((8, 8, 8, 0.1, 0.1, 0), {"flags": 1}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 0), {"flags": 2}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"rel_tol": float("nan")}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"tile_x": 48}, hj.HJ_ERR_UNSUPPORTED),
     ((8, 8, 8, 0.1, 0.1, 0), {"tile_y": 128}, hj.HJ_ERR_UNSUPPORTED),
@@ -99,7 +99,7 @@ def test_status_strings_and_defaults():
     assert lib.hj_status_string(2) == b"HJ_ERR_NOT_CONVERGED"
     p = _params()
     assert (p.tile_x, p.tile_y, p.s, p.method, p.check_every) == (32, 32, 16, 0, 32)
-    assert p.rel_tol == 1e-6 and p.flags == 0
+    assert p.rel_tol == 1e-6 and p.flags == 0 and hj.HJ_FLAG_LDS_KERNEL == 1
 
 
 @pytest.mark.parametrize("n,t,o", [(4096, 32, 0), (4096, 32, 4), (1000, 64, 6), (7, 32, 0), (12, 4, 2)])

@@ -43,10 +43,10 @@ def rel(a, b):
 
 
 def gpu_cycles_2d(f, x0, h, tile, s, ncyc, overlap=(0, 0), dtype=torch.float64, method="hierarchical",
-                  hy=None):
+                  hy=None, lds_kernel=False):
     F, X = dev(f, dtype), dev(x0, dtype)
     info = hj.solve_2d(F, X, hx=h, hy=hy if hy else h, tile=tile, s=s, overlap=overlap, method=method,
-                       rel_tol=0.0, max_cycles=ncyc)
+                       rel_tol=0.0, max_cycles=ncyc, lds_kernel=lds_kernel)
     assert info.cycles == ncyc
     return host(X), info
 
@@ -100,6 +100,41 @@ def test_cycle2d_anisotropic_spacing(orc):
         got, _ = gpu_cycles_2d(f, x0, hx, tile, s, nc, hy=hy)
         want = orc.hier_2d(f, x0, hx, hy, tile, s, nc)
         assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("tile", [(32, 16), (32, 32), (64, 16), (64, 32)])
+@pytest.mark.parametrize("overlap", [(0, 0), (4, 4), (6, 2)])
+def test_register_and_lds_kernels_match_oracle(orc, tile, overlap):
+    """Full tiles of the register-resident shapes: both cycle kernels, several
+    s (odd and even), a non-square grid that forces a right-aligned last tile."""
+    ny, nx = 150, 200
+    f = W.rhs_random((ny, nx), tile[0] + 3 * tile[1] + overlap[0])
+    x0 = W.rhs_random((ny, nx), 7)
+    h = 1.0 / 201
+    for s, nc in ((1, 2), (2, 3), (7, 2), (16, 2)):
+        say(f"reg/lds tile={tile} ov={overlap} s={s} nc={nc}")
+        want = orc.hier_2d(f, x0, h, h, tile, s, nc, overlap)
+        got, _ = gpu_cycles_2d(f, x0, h, tile, s, nc, overlap)
+        assert np.array_equal(got, want), "register kernel"
+        got_lds, _ = gpu_cycles_2d(f, x0, h, tile, s, nc, overlap, lds_kernel=True)
+        assert np.array_equal(got_lds, want), "LDS kernel"
+
+
+@pytest.mark.parametrize("tile", [(32, 32), (64, 32)])
+def test_register_kernel_solve_and_fp32(orc, tile):
+    f = W.rhs_2d_modes(256, 256, 16, 0.1, 4)
+    h = 1.0 / 257
+    x0 = np.zeros_like(f)
+    X = dev(x0)
+    info = hj.solve_2d(dev(f), X, h, tile=tile, s=8, rel_tol=1e-6)
+    xo, co, relo, _ = orc.solve_2d(f, x0, h, h, tile=tile, s=8, tol=1e-6)
+    assert info.cycles == co
+    assert np.array_equal(host(X), xo)
+    assert abs(info.rel_residual - relo) <= 1e-12 * relo
+    got, _ = gpu_cycles_2d(f, x0, h, tile, 16, 40, dtype=torch.float32)
+    assert rel(got, orc.hier_2d(f, x0, h, h, tile, 16, 40)) <= 1e-5
+    aniso, _ = gpu_cycles_2d(f, x0, h, tile, 5, 3, hy=1.0 / 129)
+    assert np.array_equal(aniso, orc.hier_2d(f, x0, h, 1.0 / 129, tile, 5, 3))
 
 
 @pytest.mark.parametrize("shape", [(512, 512), (77, 100), (1, 1), (200, 3)])
