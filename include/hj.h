@@ -101,7 +101,8 @@ typedef struct hj_params {
     int32_t method;      /* hj_method */
     int64_t max_cycles;  /* >= 1: cycles (HJ_GLOBAL: sweeps) allowed */
     int32_t check_every; /* cycles enqueued between host polls of the device-side
-                            convergence flag; 0 = 32.  Does not change results. */
+                            convergence flag; 0 = adaptive (about 0.5 ms of GPU work
+                            per poll).  Does not change results. */
     int32_t flags;       /* 0, or HJ_FLAG_LDS_KERNEL */
     double rel_tol;      /* > 0: stop at the first cycle c with ||r_c|| <= rel_tol ||r_0||.
                             <= 0: run exactly max_cycles cycles with no residual
@@ -116,7 +117,7 @@ typedef struct hj_info {
 } hj_info;
 
 /* Fill *p with defaults: 32 (x 32) tiles, no overlap, s = 16, hierarchical,
- * max_cycles = 1000000, check_every = 32, rel_tol = 1e-6. */
+ * max_cycles = 1000000, check_every = 0 (adaptive), rel_tol = 1e-6. */
 void hj_params_default(hj_params *p);
 
 /* 1D solve (Sec. 3).  n >= 1 interior points, spacing h > 0.  f: n values,

@@ -3,6 +3,8 @@
 // flag (declarations and contracts in include/hj.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdint>
@@ -169,7 +171,6 @@ hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_para
     void *bufs[3] = {xu, xs, (char *)xs + xbytes};
     double *part[2] = {S.partials, S.partials + S.npart / 2};
     const int64_t maxc = p.max_cycles;
-    const int batch = p.check_every > 0 ? p.check_every : 32;
     hj_status r;
     HJ_HIP(hj::launch_ctrl_init(S.ctrl, stream));
     int64_t final_c = maxc;
@@ -187,6 +188,11 @@ hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_para
     } else {
         const double tol = p.rel_tol;
         int64_t next = 0;
+        // check_every > 0: fixed batch.  0: batches sized to about kBatchUs of
+        // GPU time from the cycle rate observed between polls, so that at most
+        // a batch or two of early-exit launches follow convergence.
+        constexpr double kBatchUs = 500.0;
+        int64_t batch = p.check_every > 0 ? p.check_every : 4;
         auto enqueue = [&](int slot) -> hj_status {
             const int64_t k = std::min<int64_t>(batch, maxc - next);
             for (int64_t i = 0; i < k; ++i) {
@@ -195,17 +201,31 @@ hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_para
                 HJ_HIP(st.cycle(bufs[cc % 3], bufs[(cc + 1) % 3], true, tol, red));
             }
             next += k;
+            S.host[slot].iter = -1;
             HJ_HIP(hipMemcpyAsync(&S.host[slot], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
             HJ_HIP(hipEventRecord(S.ev[slot], stream));
             return HJ_OK;
         };
         if ((r = enqueue(0)) != HJ_OK) return r;
         int slot = 0;
+        auto t_prev = std::chrono::steady_clock::now();
+        int64_t iter_prev = 0;
         for (;;) {
             const bool more = next < maxc;
             if (more && (r = enqueue(slot ^ 1)) != HJ_OK) return r;  // keep the GPU fed
             HJ_HIP(hipEventSynchronize(S.ev[slot]));
             if (S.host[slot].status != hj::ST_RUNNING || !more) break;
+            if (p.check_every == 0) {
+                const auto t_now = std::chrono::steady_clock::now();
+                const int64_t done = S.host[slot].iter - iter_prev;
+                const double us = std::chrono::duration<double, std::micro>(t_now - t_prev).count();
+                if (done > 0 && us > 0.0) {
+                    const double per = us / (double)done;
+                    batch = std::max<int64_t>(4, std::min<int64_t>(256, (int64_t)(kBatchUs / per)));
+                }
+                t_prev = t_now;
+                iter_prev = S.host[slot].iter;
+            }
             slot ^= 1;
         }
         if ((r = read_ctrl(S, stream, c)) != HJ_OK) return r;
@@ -283,7 +303,7 @@ void hj_params_default(hj_params *p)
     p->s = 16;
     p->method = HJ_HIERARCHICAL;
     p->max_cycles = 1000000;
-    p->check_every = 32;
+    p->check_every = 0;
     p->rel_tol = 1e-6;
 }
 

@@ -115,7 +115,7 @@ def axis_tiles(n: int, tile: int, overlap: int = 0) -> int:
 
 
 def make_params(tile=32, s=16, method="hierarchical", rel_tol=1e-6, max_cycles=1_000_000,
-                check_every=32, overlap=0, lds_kernel=False) -> Params:
+                check_every=0, overlap=0, lds_kernel=False) -> Params:
     p = Params()
     load().hj_params_default(ctypes.byref(p))
     tx, ty = (tile, tile) if isinstance(tile, int) else tile
@@ -165,7 +165,7 @@ def _raise_or_info(st: int, info: _Info, allow_not_converged: bool) -> Info:
 
 
 def solve_1d(f, x, h, *, tile=32, s=16, method="hierarchical", rel_tol=1e-6, max_cycles=1_000_000,
-             check_every=32, overlap=0, allow_not_converged=False) -> Info:
+             check_every=0, overlap=0, allow_not_converged=False) -> Info:
     """Solve -u'' = f (n interior points, spacing h) in place in x (hj_solve_1d)."""
     _check_pair(f, x)
     if f.dim() != 1 or not f.is_contiguous() or not x.is_contiguous():
@@ -179,7 +179,7 @@ def solve_1d(f, x, h, *, tile=32, s=16, method="hierarchical", rel_tol=1e-6, max
 
 
 def solve_2d(f, x, h=None, *, hx=None, hy=None, tile=(32, 32), s=16, method="hierarchical",
-             rel_tol=1e-6, max_cycles=1_000_000, check_every=32, overlap=(0, 0),
+             rel_tol=1e-6, max_cycles=1_000_000, check_every=0, overlap=(0, 0),
              allow_not_converged=False, lds_kernel=False) -> Info:
     """Solve the 5-point Poisson system in place in x, f and x of shape (ny, nx) (hj_solve_2d).
     lds_kernel=True forces the LDS ping-pong cycle kernel (same iterates)."""

@@ -98,7 +98,7 @@ def test_status_strings_and_defaults():
     assert lib.hj_status_string(0) == b"HJ_OK"
     assert lib.hj_status_string(2) == b"HJ_ERR_NOT_CONVERGED"
     p = _params()
-    assert (p.tile_x, p.tile_y, p.s, p.method, p.check_every) == (32, 32, 16, 0, 32)
+    assert (p.tile_x, p.tile_y, p.s, p.method, p.check_every) == (32, 32, 16, 0, 0)
     assert p.rel_tol == 1e-6 and p.flags == 0 and hj.HJ_FLAG_LDS_KERNEL == 1
 
 

@@ -277,6 +277,24 @@ def test_4096_time_to_tolerance_workload_matches_oracle(orc):
     assert np.array_equal(host(X0), xo0)
 
 
+def test_4096_benchmark_setting_matches_oracle(orc):
+    """The benchmark's default setting (64 x 32 tiles, s = 8, overlap 14) on the
+    4096^2 workload: fixed cycles and the solve to 1e-6 against the oracle."""
+    f, h = W.make("poisson2d_4096", 2)
+    x0 = np.zeros_like(f)
+    say("4096^2 fixed 2 cycles T=64x32 s=8 o=14")
+    got, _ = gpu_cycles_2d(f, x0, h, (64, 32), 8, 2, (14, 14))
+    assert np.array_equal(got, orc.hier_2d(f, x0, h, h, (64, 32), 8, 2, (14, 14)))
+    X = dev(x0)
+    say("4096^2 solve to 1e-6, T=64x32 s=8 o=14")
+    info = hj.solve_2d(dev(f), X, h, tile=(64, 32), s=8, overlap=(14, 14), rel_tol=1e-6)
+    xo, co, relo, _ = orc.solve_2d(f, x0, h, h, tile=(64, 32), s=8, overlap=(14, 14), tol=1e-6,
+                                   max_cycles=1000)
+    assert info.cycles == co
+    assert np.array_equal(host(X), xo)
+    assert abs(info.rel_residual - relo) <= 1e-12 * relo
+
+
 # ------------------------------------------------------------------ contracts
 
 def test_resume_equals_one_longer_run():

@@ -306,6 +306,42 @@ def test_single_tile_is_s_plain_sweeps(orc):
                               orc.jacobi_2d(f2, x2, 0.03, 0.03, 2 * s))
 
 
+@pytest.mark.parametrize("shape", [(77, 100), (64, 130), (200, 33)])
+@pytest.mark.parametrize("tile", [(32, 32), (64, 32), (16, 16)])
+def test_overlap_beyond_halo_reach_is_exactly_classical(orc, shape, tile):
+    """A frozen edge value is stale from the second sub-iteration on, and the
+    error it injects moves one point per sweep, so after s sweeps the points at
+    distance >= s from every frozen edge carry exact classical iterates.  The
+    overlap rule (Sec. 3.5 / 4.3) puts the owned points ceil(o/2) + 1 away from
+    the edges: with o >= 2s - 2 a cycle is exactly s classical sweeps, and with
+    o = 2s - 3 it is not.  Pins the halo freezing and the ownership split."""
+    ny, nx = shape
+    f = W.rhs_random(shape, 3)
+    x0 = W.rhs_random(shape, 4)
+    h = 1.0 / (max(shape) + 1)
+    for s in (1, 2, 3, 4, 5, 8):
+        o = 2 * s - 2
+        if o >= min(tile):
+            continue
+        want = orc.jacobi_2d(f, x0, h, h, 3 * s)
+        for oo in (o, o + 1):
+            if oo < min(tile):
+                assert np.array_equal(orc.hier_2d(f, x0, h, h, tile, s, 3, (oo, oo)), want)
+        if s >= 2:
+            assert not np.array_equal(orc.hier_2d(f, x0, h, h, tile, s, 3, (o - 1, o - 1)), want)
+
+
+def test_overlap_beyond_halo_reach_1d(orc):
+    n = 333
+    f, x0 = W.rhs_random(n, 5), W.rhs_random(n, 6)
+    h = 1.0 / (n + 1)
+    for t in (32, 64):
+        for s in (2, 4, 7):
+            want = orc.jacobi_1d(f, x0, h, 4 * s)
+            assert np.array_equal(orc.hier_1d(f, x0, h, t, s, 4, 2 * s - 2), want)
+            assert not np.array_equal(orc.hier_1d(f, x0, h, t, s, 4, 2 * s - 3), want)
+
+
 # ----------------------------------------------------------------- P6: dense brute force
 
 @pytest.mark.parametrize("n,t,o,s", [(8, 4, 0, 1), (8, 4, 0, 2), (8, 4, 0, 3), (8, 4, 0, 5),
