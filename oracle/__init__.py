@@ -57,6 +57,11 @@ def _load():
         "orc_solve_2d": (_i64, [_i64, _i64, _f64, _f64, _pd, _pd, _i32, _i64, _i64, _i64, _i64,
                                 _i64, _f64, _i64, _pd, _pd]),
         "orc_num_threads": (_i32, []),
+        "orc_vc_apply_2d": (None, [_i64, _i64, _f64, _f64, _pd, _pd, _pd]),
+        "orc_vc_residual_2d": (_f64, [_i64, _i64, _f64, _f64, _pd, _pd, _pd, _pd]),
+        "orc_vc_solve_2d": (_i64, [_i64, _i64, _f64, _f64, _pd, _pd, _pd, _i32, _i64, _i64, _i64,
+                                   _i64, _i64, _f64, _i64, _pd, _pd]),
+        "orc_vc_grad_a_2d": (None, [_i64, _i64, _f64, _f64, _pd, _pd, _pd]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -180,6 +185,62 @@ def solve_2d(f, x0, hx, hy, method=HIERARCHICAL, tile=(32, 32), s=16, tol=1e-6,
     c = _load().orc_solve_2d(nx, ny, hx, hy, _p(f), _p(x), int(method), tx, ty, ox, oy, int(s),
                              float(tol), int(max_cycles), ctypes.byref(rel), ctypes.byref(r0))
     return x, int(c), rel.value, r0.value
+
+
+# ---------------------------------------------------------------- variable coefficients
+# a: node coefficients on the (ny+2, nx+2) grid including boundary nodes.
+
+def _a_arr(a, ny, nx):
+    return _arr(a, (ny + 2, nx + 2))
+
+
+def vc_apply_2d(a, u, hx, hy):
+    """A(a) u for -div(a grad u) with arithmetic-mean face coefficients."""
+    u = _arr(u)
+    ny, nx = u.shape
+    a = _a_arr(a, ny, nx)
+    out = np.empty_like(u)
+    _load().orc_vc_apply_2d(nx, ny, hx, hy, _p(a), _p(u), _p(out))
+    return out
+
+
+def vc_residual_2d(a, f, u, hx, hy):
+    f = _arr(f)
+    ny, nx = f.shape
+    a = _a_arr(a, ny, nx)
+    u = _arr(u, f.shape)
+    r = np.empty_like(f)
+    nrm = _load().orc_vc_residual_2d(nx, ny, hx, hy, _p(a), _p(f), _p(u), _p(r))
+    return r, float(nrm)
+
+
+def vc_solve_2d(a, f, x0, hx, hy, method=HIERARCHICAL, tile=(32, 32), s=8, tol=1e-10,
+                max_cycles=10**6, overlap=(0, 0)):
+    """Returns (x, cycles or -1, rel_residual, r0_norm); tol <= 0 runs max_cycles cycles."""
+    f = _arr(f)
+    ny, nx = f.shape
+    a = _a_arr(a, ny, nx)
+    x = _arr(x0, f.shape).copy()
+    tx, ty = tile
+    ox, oy = overlap
+    if method == HIERARCHICAL:
+        _check_tile(tx, ox, s)
+        _check_tile(ty, oy, s)
+    rel, r0 = _f64(), _f64()
+    c = _load().orc_vc_solve_2d(nx, ny, hx, hy, _p(a), _p(f), _p(x), int(method), tx, ty, ox, oy,
+                                int(s), float(tol), int(max_cycles), ctypes.byref(rel),
+                                ctypes.byref(r0))
+    return x, int(c), rel.value, r0.value
+
+
+def vc_grad_a_2d(u, lam, hx, hy):
+    """dL/da for A(a) u = f given the adjoint lam (A lam = dL/du)."""
+    u = _arr(u)
+    ny, nx = u.shape
+    lam = _arr(lam, u.shape)
+    g = np.empty((ny + 2, nx + 2))
+    _load().orc_vc_grad_a_2d(nx, ny, hx, hy, _p(u), _p(lam), _p(g))
+    return g
 
 
 def _check_tile(t, o, s):

@@ -442,3 +442,203 @@ int32_t orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ================================================================== */
+/* Variable-coefficient diffusion -div(a grad u) = f (general tridiagonal /
+ * pentadiagonal Jacobi of Sec. 3 and Sec. 4 with per-point coefficients).
+ *
+ * a: node values on the (ny+2) x (nx+2) grid including the boundary nodes,
+ * row-major with pitch nx+2; node (r, q) of the interior is a[(r+1)(nx+2)+q+1].
+ * Face coefficients are arithmetic means of the two nodes they join.
+ *   (A u)_rq = [aW (u - u_W) + aE (u - u_E)] / hx^2 + [aS (u - u_S) + aN (u - u_N)] / hy^2
+ * with u = 0 outside the domain.  A is symmetric positive definite.
+ * Jacobi update (Sec. 2.1 elemental form):
+ *   u <- (f + ((aW u_W + aE u_E) / hx^2 + (aS u_S + aN u_N) / hy^2)) / dsum,
+ *   dsum = (aW + aE) / hx^2 + (aS + aN) / hy^2.
+ * ================================================================== */
+
+typedef struct {
+    double w, e, s, n, dinv;  /* face weights (already / h^2) and 1/diagonal */
+} vc_coef;
+
+static vc_coef vc_at(int64_t nx, double ihx2, double ihy2, const double *a, int64_t r, int64_t q)
+{
+    int64_t p = nx + 2;
+    int64_t c = (r + 1) * p + (q + 1);
+    vc_coef k;
+    k.w = 0.5 * (a[c] + a[c - 1]) * ihx2;
+    k.e = 0.5 * (a[c] + a[c + 1]) * ihx2;
+    k.s = 0.5 * (a[c] + a[c - p]) * ihy2;
+    k.n = 0.5 * (a[c] + a[c + p]) * ihy2;
+    k.dinv = 1.0 / ((k.w + k.e) + (k.s + k.n));
+    return k;
+}
+
+static double vc_upd(const vc_coef *k, double f, double uw, double ue, double us, double un)
+{
+    return (f + ((k->w * uw + k->e * ue) + (k->s * us + k->n * un))) * k->dinv;
+}
+
+/* out = A u */
+void orc_vc_apply_2d(int64_t nx, int64_t ny, double hx, double hy, const double *a, const double *u,
+                     double *out)
+{
+    double ihx2 = 1.0 / (hx * hx), ihy2 = 1.0 / (hy * hy);
+    #pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < ny; ++r) {
+        for (int64_t q = 0; q < nx; ++q) {
+            vc_coef k = vc_at(nx, ihx2, ihy2, a, r, q);
+            double c = u[r * nx + q];
+            double uw = q > 0 ? u[r * nx + q - 1] : 0.0;
+            double ue = q < nx - 1 ? u[r * nx + q + 1] : 0.0;
+            double us = r > 0 ? u[(r - 1) * nx + q] : 0.0;
+            double un = r < ny - 1 ? u[(r + 1) * nx + q] : 0.0;
+            out[r * nx + q] = (k.w * (c - uw) + k.e * (c - ue)) + (k.s * (c - us) + k.n * (c - un));
+        }
+    }
+}
+
+double orc_vc_residual_2d(int64_t nx, int64_t ny, double hx, double hy, const double *a,
+                          const double *f, const double *u, double *r)
+{
+    double *rr = r ? r : (double *)calloc((size_t)(nx * ny), sizeof(double));
+    orc_vc_apply_2d(nx, ny, hx, hy, a, u, rr);
+    for (int64_t i = 0; i < nx * ny; ++i) rr[i] = f[i] - rr[i];
+    double nrm = norm2_compensated(rr, nx * ny);
+    if (!r) free(rr);
+    return nrm;
+}
+
+static void vc_jacobi_sweep(int64_t nx, int64_t ny, double ihx2, double ihy2, const double *a,
+                            const double *f, const double *cur, double *nxt)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < ny; ++r) {
+        for (int64_t q = 0; q < nx; ++q) {
+            vc_coef k = vc_at(nx, ihx2, ihy2, a, r, q);
+            double uw = q > 0 ? cur[r * nx + q - 1] : 0.0;
+            double ue = q < nx - 1 ? cur[r * nx + q + 1] : 0.0;
+            double us = r > 0 ? cur[(r - 1) * nx + q] : 0.0;
+            double un = r < ny - 1 ? cur[(r + 1) * nx + q] : 0.0;
+            nxt[r * nx + q] = vc_upd(&k, f[r * nx + q], uw, ue, us, un);
+        }
+    }
+}
+
+/* one hierarchical cycle for the variable-coefficient operator (Sec. 4.1 steps) */
+static void vc_hier_cycle(int64_t nx, int64_t ny, double ihx2, double ihy2, const double *a,
+                          const double *f, const double *xin, double *xout, int64_t tx, int64_t ty,
+                          int64_t ox, int64_t oy, int64_t s)
+{
+    int64_t ntx = orc_axis_ntiles(nx, tx, ox), nty = orc_axis_ntiles(ny, ty, oy);
+    int64_t ex = axis_extent(nx, tx), ey = axis_extent(ny, ty);
+    int64_t p = ex + 2;
+    #pragma omp parallel for schedule(static)
+    for (int64_t tid = 0; tid < ntx * nty; ++tid) {
+        int64_t bi = tid / ntx, bj = tid % ntx;
+        int64_t r0 = orc_axis_start(ny, ty, oy, bi);
+        int64_t c0 = orc_axis_start(nx, tx, ox, bj);
+        double *L[2];
+        L[0] = (double *)malloc(sizeof(double) * (size_t)(p * (ey + 2)));
+        L[1] = (double *)malloc(sizeof(double) * (size_t)(p * (ey + 2)));
+        for (int64_t r = -1; r <= ey; ++r) {
+            for (int64_t q = -1; q <= ex; ++q) {
+                int64_t gr = r0 + r, gq = c0 + q;
+                double v = (gr >= 0 && gr < ny && gq >= 0 && gq < nx) ? xin[gr * nx + gq] : 0.0;
+                L[0][(r + 1) * p + (q + 1)] = v;
+                L[1][(r + 1) * p + (q + 1)] = v;
+            }
+        }
+        for (int64_t k = 0; k < s; ++k) {
+            const double *src = L[k % 2];
+            double *dst = L[(k + 1) % 2];
+            for (int64_t r = 0; r < ey; ++r) {
+                for (int64_t q = 0; q < ex; ++q) {
+                    int64_t c = (r + 1) * p + (q + 1);
+                    vc_coef kk = vc_at(nx, ihx2, ihy2, a, r0 + r, c0 + q);
+                    dst[c] = vc_upd(&kk, f[(r0 + r) * nx + (c0 + q)], src[c - 1], src[c + 1],
+                                    src[c - p], src[c + p]);
+                }
+            }
+        }
+        const double *res = L[s % 2];
+        int64_t rlo, rhi, qlo, qhi;
+        orc_axis_owned(ny, ty, oy, bi, &rlo, &rhi);
+        orc_axis_owned(nx, tx, ox, bj, &qlo, &qhi);
+        for (int64_t gr = rlo; gr < rhi; ++gr)
+            for (int64_t gq = qlo; gq < qhi; ++gq)
+                xout[gr * nx + gq] = res[(gr - r0 + 1) * p + (gq - c0 + 1)];
+        free(L[0]);
+        free(L[1]);
+    }
+}
+
+/* method 0: hierarchical (tile, overlap, s); 1: classical.  ncycles >= 0 fixed
+ * cycles when tol <= 0, else to tolerance (checked every cycle).  Returns the
+ * cycle count (or -1 if max_cycles ran out), like orc_solve_2d. */
+int64_t orc_vc_solve_2d(int64_t nx, int64_t ny, double hx, double hy, const double *a,
+                        const double *f, double *x, int32_t method, int64_t tx, int64_t ty,
+                        int64_t ox, int64_t oy, int64_t s, double tol, int64_t max_cycles,
+                        double *rel_out, double *r0_out)
+{
+    double ihx2 = 1.0 / (hx * hx), ihy2 = 1.0 / (hy * hy);
+    size_t bytes = sizeof(double) * (size_t)(nx * ny);
+    double *y = (double *)malloc(bytes);
+    double *cur = x, *nxt = y;
+    double r0 = orc_vc_residual_2d(nx, ny, hx, hy, a, f, cur, NULL);
+    double rel = r0 > 0.0 ? 1.0 : 0.0;
+    int64_t c = 0, done = -1;
+    for (;;) {
+        if (tol > 0.0 && rel <= tol) { done = c; break; }
+        if (c == max_cycles) break;
+        if (method == 1) vc_jacobi_sweep(nx, ny, ihx2, ihy2, a, f, cur, nxt);
+        else vc_hier_cycle(nx, ny, ihx2, ihy2, a, f, cur, nxt, tx, ty, ox, oy, s);
+        double *tmp = cur; cur = nxt; nxt = tmp;
+        ++c;
+        if (tol > 0.0 || c == max_cycles) {
+            double rn = orc_vc_residual_2d(nx, ny, hx, hy, a, f, cur, NULL);
+            rel = r0 > 0.0 ? rn / r0 : 0.0;
+            if (!(rel == rel) || isinf(rel)) break;
+        }
+    }
+    if (cur != x) memcpy(x, cur, bytes);
+    free(y);
+    if (rel_out) *rel_out = rel;
+    if (r0_out) *r0_out = r0;
+    return tol > 0.0 ? done : c;
+}
+
+/* Gradient of a loss L(u) with A(a) u = f with respect to the node values a,
+ * given the forward state u and the adjoint lam (A lam = dL/du; A symmetric):
+ *   dL/da = -lam^T (dA/da) u.
+ * Every face between nodes P and Q carries w (u_P - u_Q)(lam_P - lam_Q) / h^2
+ * (boundary nodes have u = lam = 0), with w = 1/2 for each of the two nodes in
+ * the arithmetic-mean face coefficient.  grad has the layout of a. */
+void orc_vc_grad_a_2d(int64_t nx, int64_t ny, double hx, double hy, const double *u,
+                      const double *lam, double *grad)
+{
+    int64_t p = nx + 2;
+    double ihx2 = 1.0 / (hx * hx), ihy2 = 1.0 / (hy * hy);
+    memset(grad, 0, sizeof(double) * (size_t)(p * (ny + 2)));
+    /* node value (r, q) of the extended grid; 0 on the boundary */
+#define U_AT(R, Q) (((R) >= 0 && (R) < ny && (Q) >= 0 && (Q) < nx) ? u[(R) * nx + (Q)] : 0.0)
+#define L_AT(R, Q) (((R) >= 0 && (R) < ny && (Q) >= 0 && (Q) < nx) ? lam[(R) * nx + (Q)] : 0.0)
+    /* x faces: between (r, q) and (r, q + 1), q = -1 .. nx - 1, interior rows */
+    for (int64_t r = 0; r < ny; ++r) {
+        for (int64_t q = -1; q < nx; ++q) {
+            double t = -(U_AT(r, q) - U_AT(r, q + 1)) * (L_AT(r, q) - L_AT(r, q + 1)) * ihx2 * 0.5;
+            grad[(r + 1) * p + (q + 1)] += t;
+            grad[(r + 1) * p + (q + 2)] += t;
+        }
+    }
+    /* y faces: between (r, q) and (r + 1, q), r = -1 .. ny - 1, interior columns */
+    for (int64_t r = -1; r < ny; ++r) {
+        for (int64_t q = 0; q < nx; ++q) {
+            double t = -(U_AT(r, q) - U_AT(r + 1, q)) * (L_AT(r, q) - L_AT(r + 1, q)) * ihy2 * 0.5;
+            grad[(r + 1) * p + (q + 1)] += t;
+            grad[(r + 2) * p + (q + 1)] += t;
+        }
+    }
+#undef U_AT
+#undef L_AT
+}

@@ -54,6 +54,42 @@ def rhs_2d_modes(nx: int, ny: int | None = None, n_modes: int = 8, noise_std: fl
     return f
 
 
+def grf_2d(n_nodes_y: int, n_nodes_x: int, length: float = 0.05, variance: float = 1.0,
+           h: float | None = None, seed: int = 0) -> np.ndarray:
+    """Gaussian random field with squared-exponential covariance
+    variance * exp(-r^2 / (2 length^2)) on a grid of n_nodes_y x n_nodes_x nodes
+    with spacing h (default 1 / (n_nodes_x - 1)): white noise filtered by the
+    square root of the spectral density (periodic FFT), scaled to the target
+    variance."""
+    h = 1.0 / (n_nodes_x - 1) if h is None else h
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((n_nodes_y, n_nodes_x))
+    ky = np.fft.fftfreq(n_nodes_y, d=h)
+    kx = np.fft.fftfreq(n_nodes_x, d=h)
+    filt = np.exp(-np.pi ** 2 * length ** 2 * (ky[:, None] ** 2 + kx[None, :] ** 2))
+    g = np.real(np.fft.ifft2(np.fft.fft2(w) * filt))
+    var_theory = np.sum(filt ** 2) / (n_nodes_x * n_nodes_y)
+    return g * np.sqrt(variance / var_theory)
+
+
+def diffusion_coefficient(n: int, length: float = 0.05, variance: float = 1.0, seed: int = 0):
+    """a = exp(g) on the (n+2) x (n+2) node grid (boundary nodes included)."""
+    return np.exp(grf_2d(n + 2, n + 2, length, variance, 1.0 / (n + 1), seed))
+
+
+def smooth_modes_2d(n: int, n_modes: int = 4, kmax: int = 4, seed: int = 0) -> np.ndarray:
+    """sum of n_modes products sin(pi k x) sin(pi l y), k, l uniform in 1..kmax, N(0,1) amplitudes"""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, kmax + 1, n_modes)
+    l = rng.integers(1, kmax + 1, n_modes)
+    a = rng.standard_normal(n_modes)
+    xs = np.arange(1, n + 1) * grid_h(n)
+    u = np.zeros((n, n))
+    for km, lm, am in zip(k, l, a):
+        u += am * np.outer(np.sin(np.pi * lm * xs), np.sin(np.pi * km * xs))
+    return u
+
+
 def rhs_random(shape, seed: int = 0) -> np.ndarray:
     """Unstructured N(0,1) values, for parity cases on arbitrary shapes."""
     return np.random.default_rng(seed).standard_normal(shape)
