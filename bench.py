@@ -92,6 +92,10 @@ def main():
     ap.add_argument("--no-global", action="store_true", help="skip the global-memory baseline")
     ap.add_argument("--no-paper-config", action="store_true",
                     help="skip the paper-setting row (32 x 32 tiles, s = 16, no overlap)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32-cycles + FP64-refinement rows (to 1e-10)")
+    ap.add_argument("--mixed-tol", type=float, default=1e-10)
+    ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample budget")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
@@ -215,6 +219,9 @@ def main():
             "ms_per_seed": dict(zip(map(str, args.seeds), [round(m, 3) for m, _ in per_p[0]])),
         }
 
+    if not args.no_mixed:
+        extra["mixed_precision"] = mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args, W, cycles_h, tile, ov, s)
@@ -244,6 +251,47 @@ def main():
         **extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream):
+    """FP64 hierarchical cycles vs FP32 cycles inside FP64 iterative refinement,
+    both to args.mixed_tol on the same right-hand sides.  The FP64 path equals
+    the CPU oracle bit for bit (GPU tests); the refined solution's distance to
+    it is reported per seed."""
+    log(f"mixed precision: FP64 vs FP32 + FP64 refinement to {args.mixed_tol:g}")
+    out = {"tol": args.mixed_tol, "inner_tol": args.inner_tol, "fp64_ms": {}, "refined_ms": {},
+           "fp64_cycles": {}, "refined_inner_cycles": {}, "refined_outer": {},
+           "rel_diff_refined_vs_fp64": {}}
+    x64 = torch.zeros_like(fs[0])
+
+    def timed_call(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1), r
+
+    for sd, f, x in zip(args.seeds, fs, xs):
+        for rep in range(2):  # second call is the timed one (first warms scratch)
+            x64.zero_()
+            t64, i64 = timed_call(lambda: hj.solve_2d(f, x64, h, tile=tile, s=s, overlap=ov,
+                                                      rel_tol=args.mixed_tol))
+            x.zero_()
+            tmx, imx = timed_call(lambda: hj.solve_2d_refined(
+                f, x, h, tile=tile, s=s, overlap=ov, rel_tol=args.mixed_tol, inner_tol=args.inner_tol))
+        k = str(sd)
+        out["fp64_ms"][k] = round(t64, 3)
+        out["refined_ms"][k] = round(tmx, 3)
+        out["fp64_cycles"][k] = i64.cycles
+        out["refined_inner_cycles"][k] = imx.inner_cycles
+        out["refined_outer"][k] = imx.outer
+        out["rel_diff_refined_vs_fp64"][k] = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+    out["fp64_ms_per_problem"] = round(sum(out["fp64_ms"].values()) / len(fs), 3)
+    out["refined_ms_per_problem"] = round(sum(out["refined_ms"].values()) / len(fs), 3)
+    out["speedup_refined_vs_fp64"] = round(out["fp64_ms_per_problem"] / out["refined_ms_per_problem"], 3)
+    return out
 
 
 def calibrate_copy(torch):

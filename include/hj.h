@@ -132,6 +132,45 @@ hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *
 hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
                       const void *f, void *x, const hj_params *p, void *stream, hj_info *info);
 
+/* Mixed precision 2D solve: FP32 hierarchical cycles inside FP64 iterative
+ * refinement.  f, x: FP64 (x in/out, ld as in hj_solve_2d).
+ *
+ * Phase 1 runs FP64 cycles (inner's tile, overlap, s, method) on x until the
+ * relative residual is <= switch_tol.  Phase 2 repeats refinement steps: form
+ * r = f - A x in FP64 (stored as FP32), solve A e = r from e = 0 with FP32
+ * cycles, accumulate x += e in FP64.  A step's FP32 solve stops when its
+ * residual is <= max(inner.rel_tol * ||r||, rel_tol * ||r_0|| / 2), so it
+ * never works below what the outer tolerance needs; inner.max_cycles caps it.
+ * The solve stops when the FP64 residual meets rel_tol.
+ *
+ * The cycle is a consistent stationary iteration, so restarting it on the
+ * correction equation continues the same iteration.  FP32 rounding, however,
+ * leaves error in the slowest modes of Jacobi's iteration matrix (the
+ * smoothest and the most oscillatory), about 1e-6 times the residual at
+ * which the FP32 phase starts; those modes then take as long to remove as
+ * the slowest mode of the grid.  switch_tol keeps that residue below
+ * rel_tol.  switch_tol = 0 selects min(1, 1e4 * rel_tol); switch_tol >= 1
+ * runs FP32 from the start. */
+typedef struct hj_refine_params {
+    hj_params inner;     /* cycle shape for both phases; FP32 solve tolerances (inner.rel_tol > 0) */
+    double rel_tol;      /* > 0: outer tolerance on ||f - A x||_2 / ||f - A x_0||_2 */
+    double switch_tol;   /* >= 0: FP64 phase target (0 = default, see above) */
+    int32_t max_outer;   /* >= 1: refinement steps */
+    int32_t flags;       /* must be 0 */
+} hj_refine_params;
+
+typedef struct hj_refine_info {
+    int64_t outer;         /* refinement steps taken */
+    int64_t inner_cycles;  /* FP32 cycles over all steps */
+    int64_t fp64_cycles;   /* FP64 cycles of phase 1 */
+    double rel_residual;   /* final FP64 relative residual */
+    double r0_norm;        /* ||f - A x_0||_2 */
+} hj_refine_info;
+
+hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, double hy,
+                              const double *f, double *x, const hj_refine_params *p,
+                              void *stream, hj_refine_info *info);
+
 /* Residual r = f - A x (Sec. 3.4 / 4.2 operator) and ||r||_2 (FP64).
  * dim = 1 (uses nx = n, ny and ld ignored, hx = h) or 2.  r_out (same dtype and
  * layout as x) may be NULL; norm2_out (host) may be NULL. */
@@ -144,9 +183,53 @@ hj_status hj_residual(int32_t dim, int64_t nx, int64_t ny, int64_t ld, double hx
 hj_status hj_solve_batched(const void *desc, int64_t nprob, const hj_params *p, void *stream,
                            void *infos);
 
-/* Adjoint solve for the variable-coefficient operator.  Declared for a later
- * version; returns HJ_ERR_UNSUPPORTED. */
-hj_status hj_solve_adjoint(const void *desc, void *stream, void *info);
+/* Variable-coefficient diffusion -div(a grad u) = f on the 2D grid (the
+ * general pentadiagonal Jacobi of Sec. 4 with per-point coefficients), for a
+ * batch of right-hand sides sharing a.  a holds node values on the
+ * (ny+2) x (nx+2) grid including the boundary nodes; each face weight is the
+ * arithmetic mean of its two nodes over h^2, so A is symmetric positive
+ * definite for a > 0:
+ *   (A u)_p = sum over the 4 faces of p: a_face (u_p - u_neighbour) / h^2,
+ * u = 0 on the boundary.  Jacobi update u_p <- (f_p + sum a_face u_nb / h^2) /
+ * sum a_face / h^2; the hierarchical cycle, overlap and stopping rule are
+ * those of hj_solve_2d (no register-resident kernel: LDS ping-pong). */
+typedef struct hj_vc_problem {
+    int64_t nx, ny;        /* interior grid */
+    int64_t ld;            /* leading dimension of f, u, lam (elements, >= nx) */
+    int64_t lda;           /* leading dimension of a (elements, >= nx + 2) */
+    double hx, hy;
+    const double *a;       /* (ny + 2) rows x lda: node coefficients, FP64, device */
+    int32_t batch;         /* right-hand sides, >= 1 */
+    int32_t flags;         /* must be 0 */
+    int64_t batch_stride;  /* elements between consecutive right-hand sides, >= ny * ld */
+} hj_vc_problem;
+
+/* Solve A(a) u_b = f_b for every b (FP64; u in/out, one info per b when infos
+ * is not NULL).  Returns the worst status over the batch. */
+hj_status hj_solve_vc_2d(const hj_vc_problem *prob, const double *f, double *u, const hj_params *p,
+                         void *stream, hj_info *infos);
+
+/* dL/da for a loss L(u) with A(a) u = f, given the forward states u and the
+ * adjoint states lam (A lam = dL/du), summed over the batch:
+ *   dL/da_P = -1/2 sum over faces (P, Q) of (u_P - u_Q)(lam_P - lam_Q) / h^2
+ * (u = lam = 0 on boundary nodes).  grad: (ny + 2) rows x ld_grad (>= nx + 2). */
+hj_status hj_vc_grad_a(const hj_vc_problem *prob, const double *u, const double *lam, double *grad,
+                       int64_t ld_grad, void *stream);
+
+/* Backward pass of the variable-coefficient solve (A symmetric, so the adjoint
+ * solve is a forward solve on dL/du): lam_b <- A^-1 dL/du_b (lam holds the
+ * initial guess on entry), dL/df = lam, and dL/da into dl_da when not NULL. */
+typedef struct hj_adjoint_desc {
+    hj_vc_problem prob;
+    const double *u;       /* converged forward states (batch) */
+    const double *dl_du;   /* dL/du (batch) */
+    double *lam;           /* in: initial guess; out: adjoint states = dL/df (batch) */
+    double *dl_da;         /* out, may be NULL */
+    int64_t ld_grad;       /* leading dimension of dl_da */
+    hj_params params;      /* solver for A lam = dL/du */
+} hj_adjoint_desc;
+
+hj_status hj_solve_adjoint(const hj_adjoint_desc *d, void *stream, hj_info *infos);
 
 /* Number of tiles (workgroups of the cycle kernel) along one axis; the same
  * partition rule the kernels use.  Returns -1 on invalid arguments. */

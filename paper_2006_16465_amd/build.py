@@ -10,12 +10,12 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhj.so")
-SOURCES = ["hj_api.hip", "hj_kernels.hip"]
+SOURCES = ["hj_api.hip", "hj_kernels.hip", "hj_refine.hip", "hj_vc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
-    "-std=c++17",
+    "-std=c++20",
     "-fPIC",
     "-shared",
     # the update association is part of the result: never contract to FMA

@@ -49,6 +49,8 @@ struct DevScratch {
     size_t xbytes = 0;
     double *partials = nullptr;
     int64_t npart = 0;
+    void *rbuf = nullptr;  // mixed precision: FP32 residual and correction
+    size_t rbytes = 0;
     hj::Ctrl *ctrl = nullptr;
     hj::Ctrl *host = nullptr;  // 2 pinned slots
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -57,7 +59,7 @@ struct DevScratch {
 constexpr int kMaxDev = 64;
 DevScratch g_scr[kMaxDev];
 
-hj_status scratch_ensure(DevScratch &S, size_t xbytes, int64_t npart)
+hj_status scratch_ensure(DevScratch &S, size_t xbytes, int64_t npart, size_t rbytes = 0)
 {
     if (!S.ready) {
         HJ_HIP(hipMalloc((void **)&S.ctrl, sizeof(hj::Ctrl)));
@@ -72,6 +74,13 @@ hj_status scratch_ensure(DevScratch &S, size_t xbytes, int64_t npart)
         S.xbytes = 0;
         HJ_HIP(hipMalloc(&S.xbuf, xbytes));
         S.xbytes = xbytes;
+    }
+    if (rbytes > S.rbytes) {
+        if (S.rbuf) HJ_HIP(hipFree(S.rbuf));
+        S.rbuf = nullptr;
+        S.rbytes = 0;
+        HJ_HIP(hipMalloc(&S.rbuf, rbytes));
+        S.rbytes = rbytes;
     }
     if (npart > S.npart) {
         if (S.partials) HJ_HIP(hipFree(S.partials));
@@ -290,6 +299,80 @@ hj::Geom1 make_geom1(int64_t n, double h, const hj_params *p)
 
 constexpr int64_t kMaxAxis = (int64_t)1 << 30;
 
+hj_status check_vc_problem(const hj_vc_problem *pr)
+{
+    if (!pr) return fail(HJ_ERR_INVALID_ARG, "problem is NULL");
+    if (pr->nx < 1 || pr->ny < 1 || pr->nx > kMaxAxis || pr->ny > kMaxAxis)
+        return fail(HJ_ERR_INVALID_ARG, "nx, ny must be in [1, 2^30]");
+    if (pr->ld < pr->nx) return fail(HJ_ERR_INVALID_ARG, "ld must be >= nx");
+    if (pr->lda < pr->nx + 2) return fail(HJ_ERR_INVALID_ARG, "lda must be >= nx + 2");
+    if (!finite_pos(pr->hx) || !finite_pos(pr->hy)) return fail(HJ_ERR_INVALID_ARG, "hx, hy must be finite and > 0");
+    if (pr->batch < 1) return fail(HJ_ERR_INVALID_ARG, "batch must be >= 1");
+    if (pr->flags != 0) return fail(HJ_ERR_INVALID_ARG, "problem flags must be 0");
+    if (pr->batch > 1 && pr->batch_stride < pr->ny * pr->ld)
+        return fail(HJ_ERR_INVALID_ARG, "batch_stride must be >= ny * ld");
+    return check_ptr_dtype(pr->a, HJ_F64, "a", false);
+}
+
+hj::GeomVC make_geom_vc(const hj_vc_problem &pr, const hj_params &p)
+{
+    hj::GeomVC g;
+    g.nx = (int)pr.nx;
+    g.ny = (int)pr.ny;
+    g.ld = pr.ld;
+    g.tx = p.tile_x ? p.tile_x : 32;
+    g.ty = p.tile_y ? p.tile_y : 32;
+    g.ox = p.overlap_x;
+    g.oy = p.overlap_y;
+    g.ntx = hj::axis_count(g.nx, g.tx, g.ox);
+    g.nty = hj::axis_count(g.ny, g.ty, g.oy);
+    g.a = pr.a;
+    g.lda = pr.lda;
+    g.ihx2 = 1.0 / (pr.hx * pr.hx);
+    g.ihy2 = 1.0 / (pr.hy * pr.hy);
+    return g;
+}
+
+hj_status drive(const struct Step &st, void *xu, void *xs, size_t xbytes, const hj_params &p, int64_t spc,
+                hipStream_t stream, DevScratch &S, hj_info *info);
+
+hj_status solve_vc_locked(const hj_vc_problem &pr, const double *f, double *u, const hj_params &P,
+                          hipStream_t st, DevScratch &S, hj_info *infos)
+{
+    const hj::GeomVC g = make_geom_vc(pr, P);
+    const bool hier = P.method == HJ_HIERARCHICAL;
+    const int64_t nbc = hier ? hj::cycle_vc_blocks(g) : hj::sweep_vc_blocks(g);
+    const int64_t nbr = hj::sweep_vc_blocks(g);
+    if (nbc > INT32_MAX || nbr > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "grid too large");
+    const size_t xbytes = (size_t)pr.ny * (size_t)pr.ld * 8;
+    hj_status r;
+    if ((r = scratch_ensure(S, 2 * xbytes, 2 * std::max(nbc, nbr))) != HJ_OK) return r;
+    hj_status worst = HJ_OK;
+    for (int b = 0; b < pr.batch; ++b) {
+        const double *fb = f + (int64_t)b * pr.batch_stride;
+        double *ub = u + (int64_t)b * pr.batch_stride;
+        Step step;
+        step.nb_cycle = (int)nbc;
+        step.nb_resid = (int)nbr;
+        step.cycle = [&](const void *xi, void *xo, bool res, double tol, const hj::Red &red) {
+            return hier ? hj::launch_cycle_vc(g, P.s, res, fb, (const double *)xi, (double *)xo, red, tol, st)
+                        : hj::launch_sweep_vc(g, res, fb, (const double *)xi, (double *)xo, red, tol, st);
+        };
+        step.resid = [&](const void *xi, double *part) {
+            return hj::launch_resid_vc(g, fb, (const double *)xi, nullptr, part, st);
+        };
+        step.copy = [&](void *dst, const void *src) {
+            return hipMemcpy2DAsync(dst, (size_t)pr.ld * 8, src, (size_t)pr.ld * 8, (size_t)pr.nx * 8,
+                                    (size_t)pr.ny, hipMemcpyDeviceToDevice, st);
+        };
+        const hj_status sb = drive(step, ub, S.xbuf, xbytes, P, hier ? P.s : 1, st, S,
+                                   infos ? &infos[b] : nullptr);
+        if (sb == HJ_ERR_HIP || sb == HJ_ERR_INVALID_ARG) return sb;
+        if (sb != HJ_OK && worst == HJ_OK) worst = sb;
+    }
+    return worst;
+}
+
 }  // namespace
 
 extern "C" {
@@ -356,6 +439,144 @@ hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, 
                                 (size_t)ny, hipMemcpyDeviceToDevice, st);
     };
     return drive(step, x, S.xbuf, xbytes, P, hier ? P.s : 1, st, S, info);
+}
+
+hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, double hy,
+                              const double *f, double *x, const hj_refine_params *p,
+                              void *stream, hj_refine_info *info)
+{
+    g_err.clear();
+    if (nx < 1 || ny < 1 || nx > kMaxAxis || ny > kMaxAxis)
+        return fail(HJ_ERR_INVALID_ARG, "nx, ny must be in [1, 2^30]");
+    if (ld < nx) return fail(HJ_ERR_INVALID_ARG, "ld must be >= nx");
+    if (!finite_pos(hx) || !finite_pos(hy)) return fail(HJ_ERR_INVALID_ARG, "hx, hy must be finite and > 0");
+    hj_status r;
+    if ((r = check_ptr_dtype(f, HJ_F64, "f", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(x, HJ_F64, "x", false)) != HJ_OK) return r;
+    if (!p) return fail(HJ_ERR_INVALID_ARG, "params is NULL");
+    if (p->flags != 0) return fail(HJ_ERR_INVALID_ARG, "refine flags must be 0");
+    if (!(p->rel_tol > 0.0)) return fail(HJ_ERR_INVALID_ARG, "rel_tol must be > 0");
+    if (p->max_outer < 1) return fail(HJ_ERR_INVALID_ARG, "max_outer must be >= 1");
+    if (!(p->inner.rel_tol > 0.0)) return fail(HJ_ERR_INVALID_ARG, "inner.rel_tol must be > 0");
+    if (!(p->switch_tol >= 0.0) || !std::isfinite(p->switch_tol))
+        return fail(HJ_ERR_INVALID_ARG, "switch_tol must be finite and >= 0");
+    if ((r = check_params(&p->inner, 2)) != HJ_OK) return r;
+
+    int dev = 0;
+    HJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
+    if ((r = check_device_ptr(f, dev, "f")) != HJ_OK) return r;
+    if ((r = check_device_ptr(x, dev, "x")) != HJ_OK) return r;
+
+    DevScratch &S = g_scr[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    const hj_params P = p->inner;
+    const hj::Geom2 g = make_geom2(nx, ny, ld, hx, hy, P);
+    const bool hier = P.method == HJ_HIERARCHICAL;
+    const int64_t nbc = hier ? hj::cycle2d_blocks(g) : hj::sweep2d_blocks(g);
+    const int64_t nbr = hj::resid2d_blocks(g);
+    const int64_t nbm = hj::resid2d_mixed_blocks(g);
+    if (nbc > INT32_MAX || nbr > INT32_MAX || nbm > INT32_MAX)
+        return fail(HJ_ERR_UNSUPPORTED, "grid too large");
+    const size_t b32 = (size_t)ny * (size_t)ld * sizeof(float);
+    const size_t b64 = 2 * b32;
+    if ((r = scratch_ensure(S, 2 * b64, 2 * std::max(nbc, std::max(nbr, nbm)), 2 * b32)) != HJ_OK)
+        return r;
+    hipStream_t st = (hipStream_t)stream;
+    float *r32 = (float *)S.rbuf;
+    float *e32 = (float *)((char *)S.rbuf + b32);
+
+    Step step;  // FP32 cycles on A e = r32
+    step.nb_cycle = (int)nbc;
+    step.nb_resid = (int)nbr;
+    step.cycle = [&](const void *xi, void *xo, bool res, double tol, const hj::Red &red) {
+        return hier ? hj::launch_cycle2d(hj::F32, g, P.s, res, r32, xi, xo, red, tol, st)
+                    : hj::launch_sweep2d(hj::F32, g, res, r32, xi, xo, red, tol, st);
+    };
+    step.resid = [&](const void *xi, double *part) {
+        return hj::launch_resid2d(hj::F32, g, r32, xi, nullptr, part, st);
+    };
+    step.copy = [&](void *dst, const void *src) {
+        return hipMemcpy2DAsync(dst, (size_t)ld * 4, src, (size_t)ld * 4, (size_t)nx * 4,
+                                (size_t)ny, hipMemcpyDeviceToDevice, st);
+    };
+
+    // FP64 residual of x into r32; returns ||f - A x||^2
+    auto fp64_residual = [&](double &rsq) -> hj_status {
+        HJ_HIP(hj::launch_ctrl_init(S.ctrl, st));
+        HJ_HIP(hj::launch_resid2d_f64_to_f32(g, f, x, r32, S.partials, st));
+        HJ_HIP(hj::launch_judge(S.partials, (int)nbm, S.ctrl, 0, -1.0, st));
+        hj::Ctrl c{};
+        hj_status rr = read_ctrl(S, st, c);
+        if (rr != HJ_OK) return rr;
+        rsq = c.last_rsq;
+        return HJ_OK;
+    };
+
+    // phase 1: FP64 cycles on x down to the switch tolerance
+    const double sw = p->switch_tol > 0.0 ? p->switch_tol : std::min(1.0, 1e4 * p->rel_tol);
+    int64_t fp64_cycles = 0;
+    double r0_phase1 = 0.0;
+    if (sw < 1.0) {
+        Step s64;
+        s64.nb_cycle = (int)nbc;
+        s64.nb_resid = (int)nbr;
+        s64.cycle = [&](const void *xi, void *xo, bool res, double tol, const hj::Red &red) {
+            return hier ? hj::launch_cycle2d(hj::F64, g, P.s, res, f, xi, xo, red, tol, st)
+                        : hj::launch_sweep2d(hj::F64, g, res, f, xi, xo, red, tol, st);
+        };
+        s64.resid = [&](const void *xi, double *part) {
+            return hj::launch_resid2d(hj::F64, g, f, xi, nullptr, part, st);
+        };
+        s64.copy = [&](void *dst, const void *src) {
+            return hipMemcpy2DAsync(dst, (size_t)ld * 8, src, (size_t)ld * 8, (size_t)nx * 8,
+                                    (size_t)ny, hipMemcpyDeviceToDevice, st);
+        };
+        hj_params P64 = P;
+        P64.rel_tol = std::max(sw, p->rel_tol);
+        hj_info i64{};
+        const hj_status s1 = drive(s64, x, S.xbuf, b64, P64, hier ? P.s : 1, st, S, &i64);
+        if (s1 != HJ_OK && s1 != HJ_ERR_NOT_CONVERGED) return s1;
+        fp64_cycles = i64.cycles;
+        r0_phase1 = i64.r0_norm;
+    }
+
+    // phase 2: FP32 correction solves inside FP64 refinement.  Relative
+    // residuals stay relative to ||f - A x_0|| for the caller's x_0, which
+    // phase 1 measured if it ran.
+    double rsq = 0.0;
+    if ((r = fp64_residual(rsq)) != HJ_OK) return r;
+    double rk_norm = std::sqrt(rsq);
+    const double r0_norm = sw < 1.0 ? r0_phase1 : rk_norm;
+    double rel = r0_norm > 0.0 ? rk_norm / r0_norm : 0.0;
+    int64_t outer = 0, inner_cycles = 0;
+    hj_status status = HJ_OK;
+    while (std::isfinite(rk_norm) && rel > p->rel_tol && outer < p->max_outer) {
+        HJ_HIP(hj::launch_fill_f32(g, e32, st));
+        hj_params Pk = P;
+        Pk.rel_tol = std::max(P.rel_tol, 0.5 * p->rel_tol * r0_norm / rk_norm);
+        hj_info ii{};
+        const hj_status si = drive(step, e32, S.xbuf, b32, Pk, hier ? P.s : 1, st, S, &ii);
+        if (si != HJ_OK && si != HJ_ERR_NOT_CONVERGED) return si;
+        inner_cycles += ii.cycles;
+        HJ_HIP(hj::launch_axpy_f32_to_f64(g, e32, x, st));
+        ++outer;
+        if ((r = fp64_residual(rsq)) != HJ_OK) return r;
+        rk_norm = std::sqrt(rsq);
+        if (!std::isfinite(rk_norm)) { rel = NAN; break; }
+        rel = rk_norm / r0_norm;
+    }
+    g_err.clear();
+    if (!std::isfinite(r0_norm) || !std::isfinite(rel)) status = fail(HJ_ERR_NONFINITE, "residual norm became non-finite");
+    else if (rel > p->rel_tol) status = fail(HJ_ERR_NOT_CONVERGED, "max_outer reached before rel_tol");
+    if (info) {
+        info->outer = outer;
+        info->inner_cycles = inner_cycles;
+        info->fp64_cycles = fp64_cycles;
+        info->rel_residual = rel;
+        info->r0_norm = r0_norm;
+    }
+    return status;
 }
 
 hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *x,
@@ -465,9 +686,62 @@ hj_status hj_solve_batched(const void *, int64_t, const hj_params *, void *, voi
     return fail(HJ_ERR_UNSUPPORTED, "hj_solve_batched is not provided by this version");
 }
 
-hj_status hj_solve_adjoint(const void *, void *, void *)
+hj_status hj_solve_vc_2d(const hj_vc_problem *prob, const double *f, double *u, const hj_params *p,
+                         void *stream, hj_info *infos)
 {
-    return fail(HJ_ERR_UNSUPPORTED, "hj_solve_adjoint is not provided by this version");
+    g_err.clear();
+    hj_status r;
+    if ((r = check_vc_problem(prob)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(f, HJ_F64, "f", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(u, HJ_F64, "u", false)) != HJ_OK) return r;
+    if ((r = check_params(p, 2)) != HJ_OK) return r;
+    int dev = 0;
+    HJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
+    if ((r = check_device_ptr(prob->a, dev, "a")) != HJ_OK) return r;
+    if ((r = check_device_ptr(f, dev, "f")) != HJ_OK) return r;
+    if ((r = check_device_ptr(u, dev, "u")) != HJ_OK) return r;
+    DevScratch &S = g_scr[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    return solve_vc_locked(*prob, f, u, *p, (hipStream_t)stream, S, infos);
+}
+
+hj_status hj_vc_grad_a(const hj_vc_problem *prob, const double *u, const double *lam, double *grad,
+                       int64_t ld_grad, void *stream)
+{
+    g_err.clear();
+    hj_status r;
+    if ((r = check_vc_problem(prob)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(u, HJ_F64, "u", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(lam, HJ_F64, "lam", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(grad, HJ_F64, "grad", false)) != HJ_OK) return r;
+    if (ld_grad < prob->nx + 2) return fail(HJ_ERR_INVALID_ARG, "ld_grad must be >= nx + 2");
+    int dev = 0;
+    HJ_HIP(hipGetDevice(&dev));
+    if ((r = check_device_ptr(u, dev, "u")) != HJ_OK) return r;
+    if ((r = check_device_ptr(lam, dev, "lam")) != HJ_OK) return r;
+    if ((r = check_device_ptr(grad, dev, "grad")) != HJ_OK) return r;
+    if ((r = check_device_ptr(prob->a, dev, "a")) != HJ_OK) return r;
+    hj_params P;
+    hj_params_default(&P);
+    const hj::GeomVC g = make_geom_vc(*prob, P);
+    hipStream_t st = (hipStream_t)stream;
+    HJ_HIP(hj::launch_grad_a_vc(g, u, lam, prob->batch, prob->batch_stride, grad, ld_grad, st));
+    HJ_HIP(hipStreamSynchronize(st));
+    return HJ_OK;
+}
+
+hj_status hj_solve_adjoint(const hj_adjoint_desc *d, void *stream, hj_info *infos)
+{
+    g_err.clear();
+    if (!d) return fail(HJ_ERR_INVALID_ARG, "descriptor is NULL");
+    hj_status r = hj_solve_vc_2d(&d->prob, d->dl_du, d->lam, &d->params, stream, infos);
+    if (r != HJ_OK) return r;
+    if (d->dl_da) {
+        if (!d->u) return fail(HJ_ERR_INVALID_ARG, "u is NULL");
+        return hj_vc_grad_a(&d->prob, d->u, d->lam, d->dl_da, d->ld_grad, stream);
+    }
+    return HJ_OK;
 }
 
 int64_t hj_axis_tiles(int64_t n, int32_t tile, int32_t overlap)

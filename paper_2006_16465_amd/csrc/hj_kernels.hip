@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "hj_launch.h"
 
@@ -165,17 +166,27 @@ __global__ __launch_bounds__(kNT) void k_cycle2d(Geom2 g, const T *__restrict__ 
 // frozen halo sits in registers (columns -1 and TX, in the first / last lane
 // of each DPP row) and in LDS (rows -1 and TY).  Used when the grid holds at
 // least one full tile in each direction.
+//
+// Rows live in R + 1 register slots that rotate: a sweep at phase P finds
+// row i in slot (i + P) mod (R + 1) and writes the new row i into the slot of
+// the old row i - 1 (dead once the new row i is formed), so no register
+// copies are needed; the next sweep runs at phase P - 1.
+//
+// Isotropic update in FMA form: fma(S, 1/4, h^2 f / 4) with S = (W + E) +
+// (S + N) equals (h^2 f + S) * 1/4 rounded the two-step way, because scaling
+// by a power of two commutes with rounding; this holds whenever the values
+// involved are normal numbers (magnitudes above 2^-1020 in FP64).
 // ============================================================================
 constexpr int kDppRowShr1 = 0x111;  // lane i <- lane i - 1 of its 16-lane row
 constexpr int kDppRowShl1 = 0x101;  // lane i <- lane i + 1 of its 16-lane row
 
-// Lanes whose source falls outside the 16-lane row receive 0.
+// Lanes whose source falls outside the 16-lane row receive 0 (bound_ctrl).
 template <int CTRL>
 __device__ __forceinline__ double dpp_shift(double v)
 {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
@@ -183,16 +194,107 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_shift(float v)
 {
     return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
 
-// update from the already-summed pairs we = W + E and sn = S + N
-template <typename T, bool ISO>
-__device__ __forceinline__ T upd2_sum(T b, T we, T sn, T wx, T wy, T dinv)
+// s * 1/4 + b with one rounding, in the three-address VOP3 form (the compiler's
+// two-address v_fmac would first copy b, which stays live across sweeps)
+// (0.25 is not an inline constant and VOP3 takes no literal: it rides in SGPRs)
+__device__ __forceinline__ double fma_quarter(double sv, double b)
 {
-    if (ISO) return (b + (we + sn)) * T(0.25);
-    return (b + (wx * we + wy * sn)) * dinv;
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(sv), "s"(0.25), "v"(b));
+    return r;
 }
+
+__device__ __forceinline__ float fma_quarter(float sv, float b)
+{
+    float r;
+    asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(sv), "s"(0.25f), "v"(b));
+    return r;
+}
+
+template <typename T, int C, int R, bool RES, bool ISO>
+struct RegTile {
+    static constexpr int TX = 16 * C, TY = 4 * R, NS = R + 1;
+    T xs[NS][C];   // rows in rotating slots
+    T b[R][C];     // f on load; then h^2 f / 4 (iso) or f (general)
+    T up[C], dn[C];
+    const T *phw;  // W halo of the lane's rows (first lane of a DPP row) or zeros
+    const T *phe;  // E halo (last lane) or zeros
+    double rsq;
+
+    // exchange the lane's first / last rows through LDS; up / dn receive the
+    // neighbouring row groups' rows (or the frozen halo rows for groups 0 / 3)
+    template <int P>
+    __device__ __forceinline__ void exchange(T (*s_top)[TX], T (*s_bot)[TX], const T *pu,
+                                             const T *pd, int k, int lc0)
+    {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s_top[k][lc0 + c] = xs[(0 + P) % NS][c];
+            s_bot[k][lc0 + c] = xs[(R - 1 + P) % NS][c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            up[c] = pu[c];
+            dn[c] = pd[c];
+        }
+        __syncthreads();  // every lane has read before the next exchange writes
+    }
+
+    // one sub-iteration at phase P; FIRST also forms the residual of the
+    // incoming iterate over the owned points and scales f
+    template <int P, bool FIRST>
+    __device__ __forceinline__ void sweep(T hh, T wx, T wy, T dinv, double gwx, double gwy, int rlo,
+                                          int rhi, int clo, int chi)
+    {
+        T above[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) above[c] = up[c];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int cur = (i + P) % NS;
+            const int dst = (i + P + R) % NS;  // slot of the old row i - 1
+            const T wl = dpp_shift<kDppRowShr1>(xs[cur][C - 1]);
+            const T er = dpp_shift<kDppRowShl1>(xs[cur][0]);
+            const T hwi = phw[i], hei = phe[i];
+            T nw[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T w = c > 0 ? xs[cur][c - 1] : wl;
+                const T e = c < C - 1 ? xs[cur][c + 1] : er;
+                T we = w + e;
+                // the halo values are 0 except in the first / last lane of a
+                // DPP row, where the shifted value is 0: the sum stays W + E
+                if (c == 0) we = we + hwi;
+                if (c == C - 1) we = we + hei;
+                const T below = i < R - 1 ? xs[(i + 1 + P) % NS][c] : dn[c];
+                const T sn = above[c] + below;
+                if (FIRST) {
+                    if (RES && i >= rlo && i < rhi && c >= clo && c < chi) {
+                        const double wa = c > 0 ? (double)w : (double)wl + (double)hwi;
+                        const double ea = c < C - 1 ? (double)e : (double)er + (double)hei;
+                        const double xc = (double)xs[cur][c];
+                        const double rr = (double)b[i][c] -
+                                          (gwx * ((2.0 * xc - wa) - ea) +
+                                           gwy * ((2.0 * xc - (double)above[c]) - (double)below));
+                        rsq += rr * rr;
+                    }
+                    if (ISO) b[i][c] = (hh * b[i][c]) * T(0.25);
+                }
+                if (ISO) nw[c] = fma_quarter(we + sn, b[i][c]);
+                else nw[c] = (b[i][c] + (wx * we + wy * sn)) * dinv;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                above[c] = xs[cur][c];
+                xs[dst][c] = nw[c];
+            }
+        }
+    }
+};
 
 template <typename T, int C, int R, bool RES, bool ISO>
 __global__ __launch_bounds__(64) void k_cycle2d_reg(Geom2 g, const T *__restrict__ f,
@@ -200,7 +302,8 @@ __global__ __launch_bounds__(64) void k_cycle2d_reg(Geom2 g, const T *__restrict
                                                     T *__restrict__ xout, int nsub, Red red,
                                                     double tol)
 {
-    constexpr int TX = 16 * C, TY = 4 * R;
+    using Tile = RegTile<T, C, R, RES, ISO>;
+    constexpr int TX = Tile::TX, TY = Tile::TY, NS = Tile::NS;
     if (RES) {
         if (read_status(red.ctrl) != ST_RUNNING) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
@@ -209,6 +312,8 @@ __global__ __launch_bounds__(64) void k_cycle2d_reg(Geom2 g, const T *__restrict
     __shared__ T s_top[4][TX];   // first row of each row group (current sweep)
     __shared__ T s_bot[4][TX];   // last row of each row group
     __shared__ T s_halo[2][TX];  // frozen rows -1 and TY
+    __shared__ T s_hwe[2][TY];   // frozen columns -1 and TX
+    __shared__ T s_zero[R];
 
     const int lane = threadIdx.x, k = lane >> 4, j = lane & 15;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -219,18 +324,22 @@ __global__ __launch_bounds__(64) void k_cycle2d_reg(Geom2 g, const T *__restrict
     const int lr0 = k * R, lc0 = j * C;
     const int64_t base = (int64_t)(r0 + lr0) * ld + c0 + lc0;
 
-    // step 1: tile, halo and f into registers / LDS
-    T x[R][C], bh[R][C], hw[R], he[R];
+    // step 1: tile, halo and f into registers / LDS (phase 0: row i in slot i)
+    Tile t;
+    t.rsq = 0.0;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            x[i][c] = xin[base + (int64_t)i * ld + c];
-            bh[i][c] = f[base + (int64_t)i * ld + c];  // f for now, h^2 f after the residual
+            t.xs[i][c] = xin[base + (int64_t)i * ld + c];
+            t.b[i][c] = f[base + (int64_t)i * ld + c];
         }
-        hw[i] = (j == 0 && c0 > 0) ? xin[base + (int64_t)i * ld - 1] : T(0);
-        he[i] = (j == 15 && c0 + TX < g.nx) ? xin[base + (int64_t)i * ld + C] : T(0);
+        if (j == 0) s_hwe[0][lr0 + i] = c0 > 0 ? xin[base + (int64_t)i * ld - 1] : T(0);
+        if (j == 15) s_hwe[1][lr0 + i] = c0 + TX < g.nx ? xin[base + (int64_t)i * ld + C] : T(0);
     }
+    if (lane < R) s_zero[lane] = T(0);
+    t.phw = j == 0 ? &s_hwe[0][lr0] : s_zero;
+    t.phe = j == 15 ? &s_hwe[1][lr0] : s_zero;
     if (k == 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
@@ -246,90 +355,47 @@ __global__ __launch_bounds__(64) void k_cycle2d_reg(Geom2 g, const T *__restrict
     const int rhi = axis_own_end(g.ny, TY, g.oy, bi, g.nty) - r0 - lr0;
     const int clo = axis_own_begin(g.nx, TX, g.ox, bj) - c0 - lc0;
     const int chi = axis_own_end(g.nx, TX, g.ox, bj, g.ntx) - c0 - lc0;
+    const T *pu = k == 0 ? &s_halo[0][lc0] : &s_bot[k - 1][lc0];
+    const T *pd = k == 3 ? &s_halo[1][lc0] : &s_top[k + 1][lc0];
+    const T hh = T(g.hh), wx = T(g.wx), wy = T(g.wy), dinv = T(g.dinv);
 
-    const T wx = T(g.wx), wy = T(g.wy), dinv = T(g.dinv);
-    T up[C], dn[C];
-    auto exchange = [&]() {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            s_top[k][lc0 + c] = x[0][c];
-            s_bot[k][lc0 + c] = x[R - 1][c];
-        }
-        __syncthreads();
-        const T *pu = k == 0 ? &s_halo[0][lc0] : &s_bot[k - 1][lc0];
-        const T *pd = k == 3 ? &s_halo[1][lc0] : &s_top[k + 1][lc0];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            up[c] = pu[c];
-            dn[c] = pd[c];
-        }
-        __syncthreads();  // every lane has read before the next exchange writes
+    // step 2: nsub sub-iterations with the halo frozen.  The first runs at
+    // phase 0; then full rounds of NS sweeps (phases NS-1 .. 0, straight-line
+    // code, so the slot rotation costs no register moves); then the remainder.
+    auto one = [&]<int P>() {
+        t.template exchange<P>(s_top, s_bot, pu, pd, k, lc0);
+        t.template sweep<P, false>(hh, wx, wy, dinv, g.wx, g.wy, rlo, rhi, clo, chi);
     };
-
-    // One sub-iteration over the lane's rows, top to bottom, in place: prev
-    // keeps the old row above.  FIRST: bh still holds f; it also accumulates
-    // the residual of the incoming iterate over the owned points and turns f
-    // into h^2 f (iso) as it goes.
-    double rsq = 0.0;
-    const T hh = T(g.hh);
-    auto sweep = [&](auto first_tag) {
-        constexpr bool FIRST = decltype(first_tag)::value;
-        T prev[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) prev[c] = up[c];
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const T wl = dpp_shift<kDppRowShr1>(x[i][C - 1]);
-            const T er = dpp_shift<kDppRowShl1>(x[i][0]);
-            T nw[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const T w = c > 0 ? x[i][c - 1] : wl;
-                const T e = c < C - 1 ? x[i][c + 1] : er;
-                T we = w + e;
-                // the halo registers are 0 except in the first / last lane of a
-                // DPP row, where the shifted value is 0: the sum stays W + E
-                if (c == 0) we = we + hw[i];
-                if (c == C - 1) we = we + he[i];
-                const T below = i < R - 1 ? x[i + 1][c] : dn[c];
-                T b = bh[i][c];
-                if (FIRST) {
-                    if (RES && i >= rlo && i < rhi && c >= clo && c < chi) {
-                        const double wa = c > 0 ? (double)w : (double)wl + (double)hw[i];
-                        const double ea = c < C - 1 ? (double)e : (double)er + (double)he[i];
-                        const double rr = res2((double)b, (double)x[i][c], wa, ea, (double)prev[c],
-                                               (double)below, g.wx, g.wy);
-                        rsq += rr * rr;
-                    }
-                    if (ISO) b = hh * b;
-                    bh[i][c] = b;
-                }
-                nw[c] = upd2_sum<T, ISO>(b, we, prev[c] + below, wx, wy, dinv);
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                prev[c] = x[i][c];
-                x[i][c] = nw[c];
-            }
-        }
-    };
-
-    // step 2: nsub sub-iterations with the halo frozen
-    exchange();
-    sweep(std::true_type{});
-    for (int it = 1; it < nsub; ++it) {
-        exchange();
-        sweep(std::false_type{});
+    t.template exchange<0>(s_top, s_bot, pu, pd, k, lc0);
+    t.template sweep<0, true>(hh, wx, wy, dinv, g.wx, g.wy, rlo, rhi, clo, chi);
+    int it = 1;
+    for (; it + NS <= nsub; it += NS) {
+        [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
+            (one.template operator()<NS - 1 - Ps>(), ...);
+        }(std::make_integer_sequence<int, NS>{});
     }
+    const int rem = nsub - it;  // 0 <= rem < NS sweeps left, starting at phase NS - 1
+    [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
+        ((rem > Ps ? (one.template operator()<NS - 1 - Ps>(), 0) : 0), ...);
+    }(std::make_integer_sequence<int, NS - 1>{});
+    // the first sweep leaves phase NS - 1, full rounds return to it, and each
+    // remainder sweep lowers it by one
+    const int ph = NS - 1 - rem;
 
-    // step 3: owned points back to global memory
+    // step 3: owned points back to global memory (row i in slot (i + ph) mod NS)
+    [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
+        ((ph == Ps ? ([&] {
 #pragma unroll
-    for (int i = 0; i < R; ++i)
+              for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (i >= rlo && i < rhi && c >= clo && c < chi) xout[base + (int64_t)i * ld + c] = x[i][c];
+                  for (int c = 0; c < C; ++c)
+                      if (i >= rlo && i < rhi && c >= clo && c < chi)
+                          xout[base + (int64_t)i * ld + c] = t.xs[(i + Ps) % NS][c];
+          }(), 0) : 0),
+         ...);
+    }(std::make_integer_sequence<int, NS>{});
 
-    if (RES) post_partial<64>(rsq, red.part_cur);
+    if (RES) post_partial<64>(t.rsq, red.part_cur);
 }
 
 // ============================================================================

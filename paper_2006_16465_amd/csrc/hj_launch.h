@@ -65,4 +65,31 @@ hipError_t launch_judge(const double *part, int n, Ctrl *ctrl, int64_t c, double
 
 hipError_t launch_ctrl_init(Ctrl *ctrl, hipStream_t st);
 
+// variable-coefficient diffusion (hj_vc.hip)
+struct GeomVC {
+    int nx, ny;
+    int64_t ld;
+    int tx, ty, ox, oy, ntx, nty;
+    const double *a;  // (ny+2) x lda node coefficients
+    int64_t lda;
+    double ihx2, ihy2;
+};
+int64_t cycle_vc_blocks(const GeomVC &g);
+int64_t sweep_vc_blocks(const GeomVC &g);
+hipError_t launch_cycle_vc(const GeomVC &g, int s, bool res, const double *f, const double *xin,
+                           double *xout, const Red &red, double tol, hipStream_t st);
+hipError_t launch_sweep_vc(const GeomVC &g, bool res, const double *f, const double *xin, double *xout,
+                           const Red &red, double tol, hipStream_t st);
+hipError_t launch_resid_vc(const GeomVC &g, const double *f, const double *x, double *r_out,
+                           double *part, hipStream_t st);
+hipError_t launch_grad_a_vc(const GeomVC &g, const double *u, const double *lam, int nb,
+                            int64_t bstride, double *grad, int64_t ldg, hipStream_t st);
+
+// mixed precision helpers (hj_refine.hip)
+int64_t resid2d_mixed_blocks(const Geom2 &g);
+hipError_t launch_resid2d_f64_to_f32(const Geom2 &g, const double *f, const double *x, float *r32,
+                                     double *part, hipStream_t st);
+hipError_t launch_axpy_f32_to_f64(const Geom2 &g, const float *e, double *x, hipStream_t st);
+hipError_t launch_fill_f32(const Geom2 &g, float *e, hipStream_t st);
+
 }  // namespace hj

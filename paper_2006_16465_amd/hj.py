@@ -36,6 +36,40 @@ class Params(ctypes.Structure):
     ]
 
 
+class RefineParams(ctypes.Structure):
+    _fields_ = [("inner", Params), ("rel_tol", ctypes.c_double), ("switch_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class _RefineInfo(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int64), ("inner_cycles", ctypes.c_int64),
+                ("fp64_cycles", ctypes.c_int64), ("rel_residual", ctypes.c_double),
+                ("r0_norm", ctypes.c_double)]
+
+
+@dataclass
+class RefineInfo:
+    status: int
+    outer: int
+    inner_cycles: int
+    fp64_cycles: int
+    rel_residual: float
+    r0_norm: float
+
+
+class VCProblem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("hx", ctypes.c_double), ("hy", ctypes.c_double),
+                ("a", ctypes.c_void_p), ("batch", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("batch_stride", ctypes.c_int64)]
+
+
+class AdjointDesc(ctypes.Structure):
+    _fields_ = [("prob", VCProblem), ("u", ctypes.c_void_p), ("dl_du", ctypes.c_void_p),
+                ("lam", ctypes.c_void_p), ("dl_da", ctypes.c_void_p), ("ld_grad", ctypes.c_int64),
+                ("params", Params)]
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int64), ("sweeps", ctypes.c_int64),
                 ("rel_residual", ctypes.c_double), ("r0_norm", ctypes.c_double)]
@@ -61,8 +95,9 @@ class HJError(RuntimeError):
 
 
 _lib = None
-EXPORTS = ("hj_params_default", "hj_solve_1d", "hj_solve_2d", "hj_residual", "hj_solve_batched",
-           "hj_solve_adjoint", "hj_axis_tiles", "hj_status_string", "hj_last_error", "hj_version")
+EXPORTS = ("hj_params_default", "hj_solve_1d", "hj_solve_2d", "hj_solve_2d_refined", "hj_residual",
+           "hj_solve_batched", "hj_solve_vc_2d", "hj_vc_grad_a", "hj_solve_adjoint", "hj_axis_tiles",
+           "hj_status_string", "hj_last_error", "hj_version")
 
 
 def load():
@@ -81,11 +116,18 @@ def load():
     lib.hj_solve_1d.restype = i32
     lib.hj_solve_2d.argtypes = [i64, i64, i64, f64, f64, i32, vp, vp, P, vp, I]
     lib.hj_solve_2d.restype = i32
+    lib.hj_solve_2d_refined.argtypes = [i64, i64, i64, f64, f64, vp, vp, ctypes.POINTER(RefineParams),
+                                        vp, ctypes.POINTER(_RefineInfo)]
+    lib.hj_solve_2d_refined.restype = i32
     lib.hj_residual.argtypes = [i32, i64, i64, i64, f64, f64, i32, vp, vp, vp, ctypes.POINTER(f64), vp]
     lib.hj_residual.restype = i32
     lib.hj_solve_batched.argtypes = [vp, i64, P, vp, vp]
     lib.hj_solve_batched.restype = i32
-    lib.hj_solve_adjoint.argtypes = [vp, vp, vp]
+    lib.hj_solve_vc_2d.argtypes = [ctypes.POINTER(VCProblem), vp, vp, P, vp, I]
+    lib.hj_solve_vc_2d.restype = i32
+    lib.hj_vc_grad_a.argtypes = [ctypes.POINTER(VCProblem), vp, vp, vp, i64, vp]
+    lib.hj_vc_grad_a.restype = i32
+    lib.hj_solve_adjoint.argtypes = [ctypes.POINTER(AdjointDesc), vp, I]
     lib.hj_solve_adjoint.restype = i32
     lib.hj_axis_tiles.argtypes = [i64, i32, i32]
     lib.hj_axis_tiles.restype = i64
@@ -196,6 +238,145 @@ def solve_2d(f, x, h=None, *, hx=None, hy=None, tile=(32, 32), s=16, method="hie
         st = load().hj_solve_2d(nx, ny, ld, float(hx), float(hy), _dtype_code(f), f.data_ptr(),
                                 x.data_ptr(), ctypes.byref(p), _stream(f), ctypes.byref(info))
     return _raise_or_info(st, info, allow_not_converged)
+
+
+def solve_2d_refined(f, x, h=None, *, hx=None, hy=None, tile=(64, 32), s=8, overlap=(14, 14),
+                     method="hierarchical", rel_tol=1e-10, inner_tol=1e-4, switch_tol=0.0,
+                     inner_max_cycles=100_000, max_outer=50, check_every=0,
+                     allow_not_converged=False) -> RefineInfo:
+    """FP64 solve: FP64 cycles down to switch_tol (0 = 1e4 * rel_tol), then FP32
+    cycles inside FP64 iterative refinement (hj_solve_2d_refined).  f and x are
+    FP64 (ny, nx) tensors; x is updated in place."""
+    import torch
+    _check_pair(f, x)
+    if f.dtype != torch.float64:
+        raise TypeError("solve_2d_refined takes FP64 f and x")
+    hx = hx if hx is not None else h
+    hy = hy if hy is not None else hx
+    ld = _ld(f)
+    if _ld(x) != ld:
+        raise ValueError("f and x must share the row stride")
+    ny, nx = f.shape
+    rp = RefineParams()
+    rp.inner = make_params(tile, s, method, inner_tol, inner_max_cycles, check_every, overlap)
+    rp.rel_tol = rel_tol
+    rp.switch_tol = switch_tol
+    rp.max_outer = max_outer
+    rp.flags = 0
+    info = _RefineInfo()
+    with _device(f):
+        st = load().hj_solve_2d_refined(nx, ny, ld, float(hx), float(hy), f.data_ptr(), x.data_ptr(),
+                                        ctypes.byref(rp), _stream(f), ctypes.byref(info))
+    out = RefineInfo(st, info.outer, info.inner_cycles, info.fp64_cycles, info.rel_residual,
+                     info.r0_norm)
+    if st == HJ_OK or (st == HJ_ERR_NOT_CONVERGED and allow_not_converged):
+        return out
+    raise HJError(st, last_error())
+
+
+def _vc_problem(a, f, hx, hy):
+    """f: (ny, nx) or (batch, ny, nx) contiguous FP64; a: (ny+2, nx+2) contiguous FP64."""
+    import torch
+    if f.dtype != torch.float64 or a.dtype != torch.float64:
+        raise TypeError("variable-coefficient solves are FP64")
+    if not (f.is_cuda and a.is_cuda and f.is_contiguous() and a.is_contiguous()):
+        raise ValueError("a and f must be contiguous GPU tensors")
+    ny, nx = f.shape[-2:]
+    if tuple(a.shape) != (ny + 2, nx + 2):
+        raise ValueError(f"a must have shape {(ny + 2, nx + 2)}")
+    pr = VCProblem()
+    pr.nx, pr.ny, pr.ld, pr.lda = nx, ny, nx, nx + 2
+    pr.hx, pr.hy = float(hx), float(hy)
+    pr.a = a.data_ptr()
+    pr.batch = f.shape[0] if f.dim() == 3 else 1
+    pr.flags = 0
+    pr.batch_stride = ny * nx
+    return pr
+
+
+def solve_vc_2d(a, f, u, h=None, *, hx=None, hy=None, tile=(32, 32), s=8, overlap=(0, 0),
+                method="hierarchical", rel_tol=1e-10, max_cycles=1_000_000, check_every=0,
+                allow_not_converged=False):
+    """Solve -div(a grad u_b) = f_b for a batch (hj_solve_vc_2d); u (same shape as f) in/out.
+    Returns one Info per right-hand side."""
+    _check_pair(f, u)
+    hx = hx if hx is not None else h
+    hy = hy if hy is not None else hx
+    pr = _vc_problem(a, f, hx, hy)
+    if not u.is_contiguous():
+        raise ValueError("u must be contiguous")
+    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap)
+    infos = (_Info * pr.batch)()
+    with _device(f):
+        st = load().hj_solve_vc_2d(ctypes.byref(pr), f.data_ptr(), u.data_ptr(), ctypes.byref(p),
+                                   _stream(f), infos)
+    out = [Info(st, i.cycles, i.sweeps, i.rel_residual, i.r0_norm) for i in infos]
+    if st == HJ_OK or (st == HJ_ERR_NOT_CONVERGED and allow_not_converged):
+        return out
+    raise HJError(st, last_error())
+
+
+def vc_grad_a(a, u, lam, h=None, *, hx=None, hy=None):
+    """dL/da (shape of a) from forward states u and adjoint states lam, summed over the batch."""
+    import torch
+    hx = hx if hx is not None else h
+    hy = hy if hy is not None else hx
+    pr = _vc_problem(a, u, hx, hy)
+    if lam.shape != u.shape or not lam.is_contiguous():
+        raise ValueError("lam must match u")
+    grad = torch.empty_like(a)
+    with _device(u):
+        st = load().hj_vc_grad_a(ctypes.byref(pr), u.data_ptr(), lam.data_ptr(), grad.data_ptr(),
+                                 a.shape[1], _stream(u))
+    if st != HJ_OK:
+        raise HJError(st, last_error())
+    return grad
+
+
+def _diffusion_fn():
+    import torch
+
+    class DiffusionSolve(torch.autograd.Function):
+        """u = A(a)^-1 f for -div(a grad u) = f.  Backward: one adjoint solve
+        A lam = dL/du (A is symmetric), dL/df = lam, dL/da from the face
+        products of u and lam.  Only the converged u (and a) are stored."""
+
+        @staticmethod
+        def forward(ctx, f, a, opts):
+            f = f.contiguous()
+            a = a.contiguous()
+            u = torch.zeros_like(f)
+            solve_vc_2d(a, f, u, **opts)
+            ctx.save_for_backward(u, a)
+            ctx.opts = opts
+            return u
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            u, a = ctx.saved_tensors
+            g = grad_u.contiguous()
+            lam = torch.zeros_like(g)
+            solve_vc_2d(a, g, lam, **ctx.opts)
+            grad_a = vc_grad_a(a, u, lam, hx=ctx.opts["hx"], hy=ctx.opts["hy"])
+            return lam, grad_a, None
+
+    return DiffusionSolve
+
+
+_DIFF = None
+
+
+def diffusion_solve(f, a, h=None, *, hx=None, hy=None, tile=(32, 32), s=8, overlap=(0, 0),
+                    rel_tol=1e-10, max_cycles=1_000_000):
+    """Differentiable variable-coefficient solve (torch autograd): returns u with
+    gradients to f and a through the adjoint hierarchical solve."""
+    global _DIFF
+    if _DIFF is None:
+        _DIFF = _diffusion_fn()
+    hx = hx if hx is not None else h
+    hy = hy if hy is not None else hx
+    opts = dict(hx=hx, hy=hy, tile=tile, s=s, overlap=overlap, rel_tol=rel_tol, max_cycles=max_cycles)
+    return _DIFF.apply(f, a, opts)
 
 
 def residual(f, x, h=None, *, hx=None, hy=None, r_out=None) -> float:

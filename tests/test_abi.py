@@ -21,7 +21,8 @@ def declared_functions():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for n in ("hj_solve_1d", "hj_solve_2d", "hj_residual", "hj_solve_batched", "hj_solve_adjoint"):
+    for n in ("hj_solve_1d", "hj_solve_2d", "hj_solve_2d_refined", "hj_residual", "hj_solve_batched",
+              "hj_solve_vc_2d", "hj_vc_grad_a", "hj_solve_adjoint"):
         assert n in names
 
 
@@ -86,11 +87,61 @@ def test_solve_rejects_null_and_misaligned_pointers():
     assert lib.hj_residual(2, 8, 8, 8, 0.1, 0.1, 0, FAKE, FAKE, FAKE + 2, ctypes.byref(nrm), None) == 1
 
 
+def test_refined_solve_rejects_invalid_arguments():
+    lib = hj.load()
+    info = hj._RefineInfo()
+
+    def rp(**kw):
+        p = hj.RefineParams()
+        p.inner = _params(rel_tol=1e-4)
+        p.rel_tol, p.max_outer, p.flags = 1e-10, 10, 0
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    def call(p, nx=8, ny=8, ld=8, h=0.1):
+        return lib.hj_solve_2d_refined(nx, ny, ld, h, h, FAKE, FAKE, ctypes.byref(p), None, ctypes.byref(info))
+
+    assert call(rp(rel_tol=0.0)) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(max_outer=0)) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(flags=1)) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(switch_tol=-1e-3)) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(switch_tol=float("nan"))) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(switch_tol=float("inf"))) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(inner=_params(rel_tol=0.0))) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(inner=_params(rel_tol=1e-4, s=0))) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(inner=_params(rel_tol=1e-4, tile_x=48))) == hj.HJ_ERR_UNSUPPORTED
+    assert call(rp(), ld=4) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(), h=-1.0) == hj.HJ_ERR_INVALID_ARG
+
+
 def test_future_entry_points_report_unsupported():
     lib = hj.load()
     p = _params()
     assert lib.hj_solve_batched(None, 0, ctypes.byref(p), None, None) == hj.HJ_ERR_UNSUPPORTED
-    assert lib.hj_solve_adjoint(None, None, None) == hj.HJ_ERR_UNSUPPORTED
+
+
+def test_variable_coefficient_entry_points_validate():
+    lib = hj.load()
+    p = _params()
+
+    def prob(**kw):
+        pr = hj.VCProblem()
+        pr.nx, pr.ny, pr.ld, pr.lda, pr.hx, pr.hy = 8, 8, 8, 10, 0.1, 0.1
+        pr.a, pr.batch, pr.flags, pr.batch_stride = FAKE, 1, 0, 64
+        for k, v in kw.items():
+            setattr(pr, k, v)
+        return pr
+
+    info = (hj._Info * 4)()
+    for kw in ({"nx": 0}, {"ld": 7}, {"lda": 9}, {"hx": 0.0}, {"batch": 0}, {"flags": 1},
+               {"batch": 2, "batch_stride": 10}, {"a": None}):
+        pr = prob(**kw)
+        assert lib.hj_solve_vc_2d(ctypes.byref(pr), FAKE, FAKE, ctypes.byref(p), None, info) == \
+            hj.HJ_ERR_INVALID_ARG, kw
+    pr = prob()
+    assert lib.hj_vc_grad_a(ctypes.byref(pr), FAKE, FAKE, FAKE, 9, None) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_solve_adjoint(None, None, None) == hj.HJ_ERR_INVALID_ARG
 
 
 def test_status_strings_and_defaults():

@@ -371,6 +371,76 @@ def test_side_stream(orc):
     assert np.array_equal(host(X), orc.hier_2d(f, x0, h, h, (32, 32), 4, 6))
 
 
+# ------------------------------------------------------------------ mixed precision (FP32 cycles, FP64 refinement)
+
+def kappa_2d(n):
+    """Condition number of the 5-point Dirichlet Laplacian on an n x n grid:
+    lambda_max / lambda_min = cot^2(pi h / 2), h = 1 / (n + 1)."""
+    return 1.0 / np.tan(np.pi / (2 * (n + 1))) ** 2
+
+
+def fp64_residual_np(f, x, h):
+    xp = np.pad(x, 1)
+    ax = (4 * x - xp[1:-1, :-2] - xp[1:-1, 2:] - xp[:-2, 1:-1] - xp[2:, 1:-1]) / h ** 2
+    return np.linalg.norm(f - ax) / np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("tile,s,ov,seed", [((64, 32), 8, (14, 14), 2), ((64, 32), 8, (14, 14), 3),
+                                            ((32, 32), 16, (0, 0), 2)])
+def test_refined_solve_reaches_1e10_and_matches_fp64_oracle(orc, tile, s, ov, seed):
+    n = 256
+    f = W.rhs_2d_modes(n, n, 8, 0.0, seed)
+    h = 1.0 / (n + 1)
+    X = dev(np.zeros_like(f))
+    info = hj.solve_2d_refined(dev(f), X, h, tile=tile, s=s, overlap=ov, rel_tol=1e-10, inner_tol=1e-4,
+                               inner_max_cycles=5000, max_outer=12)
+    x = host(X)
+    rel_np = fp64_residual_np(f, x, h)  # FP64 residual of the result, formed here from the definition
+    say(f"refined {tile} s={s} ov={ov} seed={seed}: fp64 cycles={info.fp64_cycles} outer={info.outer} "
+        f"inner_cycles={info.inner_cycles} rel={info.rel_residual:.3e} (numpy {rel_np:.3e})")
+    assert info.rel_residual <= 1e-10 and rel_np <= 1.001e-10
+    assert abs(info.rel_residual - rel_np) <= 1e-3 * rel_np
+    # phase 1 is the FP64 solve to 1e4 * rel_tol: same cycle count as the oracle's
+    _, c1, _, _ = orc.solve_2d(f, np.zeros_like(f), h, h, tile=tile, s=s, overlap=ov, tol=1e-6)
+    assert info.fp64_cycles == c1
+    xo, co, relo, _ = orc.solve_2d(f, np.zeros_like(f), h, h, tile=tile, s=s, overlap=ov, tol=1e-10)
+    err = rel(x, xo)
+    bound = kappa_2d(n) * (rel_np + relo)
+    say(f"  error vs FP64 oracle solve (both to 1e-10): {err:.3e} (bound kappa*(r+r_o) {bound:.3e}); "
+        f"FP64 cycles {co}")
+    assert err <= bound
+    # restarting the cycle on the correction equation continues the same iteration
+    total = info.fp64_cycles + info.inner_cycles
+    assert abs(total - co) <= 2 * info.outer + 2 + co // 50
+
+
+def test_refined_solve_fp32_from_the_start_still_converges():
+    """switch_tol >= 1: refinement alone (no FP64 phase) reaches 1e-10; FP32
+    rounding leaves slow-mode error that costs extra cycles, which is why the
+    default starts FP32 only near rel_tol * 1e4."""
+    n = 128
+    f = W.rhs_2d_modes(n, n, 8, 0.0, 5)
+    h = 1.0 / (n + 1)
+    X = dev(np.zeros_like(f))
+    info = hj.solve_2d_refined(dev(f), X, h, tile=(32, 32), s=8, overlap=(14, 14), rel_tol=1e-10,
+                               inner_tol=1e-4, switch_tol=1.0, inner_max_cycles=20000, max_outer=20)
+    rel_np = fp64_residual_np(f, host(X), h)
+    say(f"refined from FP32 start: outer={info.outer} inner={info.inner_cycles} rel={rel_np:.3e}")
+    assert info.fp64_cycles == 0 and info.outer >= 1
+    assert info.rel_residual <= 1e-10 and rel_np <= 1.001e-10
+
+
+def test_refined_solve_reports_not_converged():
+    f = W.rhs_2d_modes(128, 128, 8, 0.0, 1)
+    X = dev(np.zeros_like(f))
+    info = hj.solve_2d_refined(dev(f), X, 1 / 129, tile=(32, 32), s=4, overlap=(0, 0), rel_tol=1e-12,
+                               inner_tol=1e-2, switch_tol=1.0, max_outer=2, allow_not_converged=True)
+    assert info.status == hj.HJ_ERR_NOT_CONVERGED and info.outer == 2
+    with pytest.raises(hj.HJError):
+        hj.solve_2d_refined(dev(f), dev(np.zeros_like(f)), 1 / 129, tile=(32, 32), s=4,
+                            overlap=(0, 0), rel_tol=1e-12, inner_tol=1e-2, switch_tol=1.0, max_outer=2)
+
+
 # ------------------------------------------------------------------ FP32 instantiation
 
 def test_fp32_iterates_within_1e5_of_fp64_oracle(orc):
