@@ -58,6 +58,18 @@ def sweep_bytes_per_launch(n, esize=8):
     return 3 * esize * n * n
 
 
+def cycle_kernel_name(tile, n):
+    """Name of the cycle kernel the library runs for this tile on an n x n
+    grid: register-resident tiles of C = tx/16 columns and R rows per lane over
+    W wavefronts (R = ty/4 up to 64 x 32; 4 rows, 8 at tx = 32, above), else
+    the LDS kernel."""
+    tx, ty = tile
+    if tx in (32, 64, 128) and ty in (16, 32, 64, 128) and n >= max(tile):
+        r = ty // 4 if (tx <= 64 and ty <= 32) else (8 if tx == 32 else 4)
+        return f"k_cycle2d_reg<double,{tx // 16},{r},{ty // (4 * r)},true,true>"
+    return f"k_cycle2d<double,{tx},{ty},true,true>"
+
+
 def kernel_source_hash():
     with open(KERNEL_SRC, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
@@ -82,9 +94,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--tile", type=int, nargs=2, default=[64, 32])
-    ap.add_argument("--s", type=int, default=8)
-    ap.add_argument("--overlap", type=int, nargs=2, default=[14, 14])
+    ap.add_argument("--tile", type=int, nargs=2, default=[64, 128])
+    ap.add_argument("--s", type=int, default=12)
+    ap.add_argument("--overlap", type=int, nargs=2, default=[22, 22])
     ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1, 2, 3, 4])
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=0, help="0: adaptive polling")
@@ -169,9 +181,7 @@ def main():
     achieved = bpl / avg_launch_s / 1e9
     kname = f"cycle2d_f64_t{tile[0]}x{tile[1]}_s{s}_o{ov[0]}x{ov[1]}_n{n}"
     traffic = load_traffic(kname)
-    reg = tile[0] in (32, 64) and tile[1] in (16, 32) and n >= max(tile)
-    kern = (f"k_cycle2d_reg<double,{tile[0] // 16},{tile[1] // 4},true,true>" if reg
-            else f"k_cycle2d<double,{tile[0]},{tile[1]},true,true>")
+    kern = cycle_kernel_name(tile, n)
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -260,7 +270,7 @@ def mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream):
     it is reported per seed."""
     log(f"mixed precision: FP64 vs FP32 + FP64 refinement to {args.mixed_tol:g}")
     out = {"tol": args.mixed_tol, "inner_tol": args.inner_tol, "fp64_ms": {}, "refined_ms": {},
-           "fp64_cycles": {}, "refined_inner_cycles": {}, "refined_outer": {},
+           "fp64_cycles": {}, "refined_fp64_cycles": {}, "refined_inner_cycles": {}, "refined_outer": {},
            "rel_diff_refined_vs_fp64": {}}
     x64 = torch.zeros_like(fs[0])
 
@@ -285,6 +295,7 @@ def mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream):
         out["fp64_ms"][k] = round(t64, 3)
         out["refined_ms"][k] = round(tmx, 3)
         out["fp64_cycles"][k] = i64.cycles
+        out["refined_fp64_cycles"][k] = imx.fp64_cycles
         out["refined_inner_cycles"][k] = imx.inner_cycles
         out["refined_outer"][k] = imx.outer
         out["rel_diff_refined_vs_fp64"][k] = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))

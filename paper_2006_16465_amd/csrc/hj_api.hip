@@ -124,7 +124,9 @@ hj_status check_params(const hj_params *p, int dim)
         if (dim == 2 && (p->overlap_y < 0 || p->overlap_y >= ty))
             return fail(HJ_ERR_INVALID_ARG, "params.overlap_y must satisfy 0 <= overlap_y < tile_y");
         if (dim == 2 && !hj::cycle2d_supported(tx, ty))
-            return fail(HJ_ERR_UNSUPPORTED, "2D tile shape not provided (tile_x, tile_y in {16, 32, 64})");
+            return fail(HJ_ERR_UNSUPPORTED,
+                        "2D tile shape not provided (tile_x, tile_y in {16, 32, 64, 128}; "
+                        "tile_x = 16 only with tile_y <= 64)");
         if (dim == 1 && !hj::cycle1d_supported(tx))
             return fail(HJ_ERR_UNSUPPORTED, "1D tile not provided (32, 64, ..., 1024)");
     }
@@ -263,6 +265,10 @@ hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_para
         return fail(HJ_ERR_NOT_CONVERGED, "max_cycles reached before rel_tol");
     return HJ_OK;
 }
+
+constexpr const char *kNeedFullTile =
+    "tiles with a 128 extent run only in the register kernel, on grids of at least one full tile "
+    "(nx >= tile_x, ny >= tile_y, no HJ_FLAG_LDS_KERNEL)";
 
 hj::Geom2 make_geom2(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, const hj_params &p)
 {
@@ -403,6 +409,8 @@ hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, 
     if ((r = check_ptr_dtype(f, dtype, "f", false)) != HJ_OK) return r;
     if ((r = check_ptr_dtype(x, dtype, "x", false)) != HJ_OK) return r;
     if ((r = check_params(p, 2)) != HJ_OK) return r;
+    if (p->method == HJ_HIERARCHICAL && !hj::cycle2d_runnable(make_geom2(nx, ny, ld, hx, hy, *p)))
+        return fail(HJ_ERR_UNSUPPORTED, kNeedFullTile);
 
     int dev = 0;
     HJ_HIP(hipGetDevice(&dev));
@@ -461,6 +469,9 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
     if (!(p->switch_tol >= 0.0) || !std::isfinite(p->switch_tol))
         return fail(HJ_ERR_INVALID_ARG, "switch_tol must be finite and >= 0");
     if ((r = check_params(&p->inner, 2)) != HJ_OK) return r;
+    if (p->inner.method == HJ_HIERARCHICAL &&
+        !hj::cycle2d_runnable(make_geom2(nx, ny, ld, hx, hy, p->inner)))
+        return fail(HJ_ERR_UNSUPPORTED, kNeedFullTile);
 
     int dev = 0;
     HJ_HIP(hipGetDevice(&dev));
@@ -695,6 +706,8 @@ hj_status hj_solve_vc_2d(const hj_vc_problem *prob, const double *f, double *u, 
     if ((r = check_ptr_dtype(f, HJ_F64, "f", false)) != HJ_OK) return r;
     if ((r = check_ptr_dtype(u, HJ_F64, "u", false)) != HJ_OK) return r;
     if ((r = check_params(p, 2)) != HJ_OK) return r;
+    if (p->method == HJ_HIERARCHICAL && ((p->tile_x ? p->tile_x : 32) > 64 || (p->tile_y ? p->tile_y : 32) > 64))
+        return fail(HJ_ERR_UNSUPPORTED, "variable-coefficient tiles are at most 64 x 64");
     int dev = 0;
     HJ_HIP(hipGetDevice(&dev));
     if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");

@@ -158,24 +158,22 @@ __global__ __launch_bounds__(kNT) void k_cycle2d(Geom2 g, const T *__restrict__ 
 }
 
 // ============================================================================
-// 2D hierarchical cycle, register-resident.  One wavefront per full tile of
-// TX = 16*C columns by TY = 4*R rows: lane 16k + j holds rows [kR, kR + R) x
-// columns [jC, jC + C) of the tile in VGPRs, so a 16-lane DPP row spans the
-// whole tile width.  x-neighbours in other lanes come from DPP row shifts;
-// y-neighbours in other row groups through four LDS interface rows.  The
-// frozen halo sits in registers (columns -1 and TX, in the first / last lane
-// of each DPP row) and in LDS (rows -1 and TY).  Used when the grid holds at
-// least one full tile in each direction.
-//
-// Rows live in R + 1 register slots that rotate: a sweep at phase P finds
-// row i in slot (i + P) mod (R + 1) and writes the new row i into the slot of
-// the old row i - 1 (dead once the new row i is formed), so no register
-// copies are needed; the next sweep runs at phase P - 1.
+// 2D hierarchical cycle, register-resident.  A workgroup of W wavefronts takes
+// one full tile of TX = 16*C columns by TY = 4*R*W rows.  Thread t belongs to
+// row group k = t / 16 (4 per wavefront, NG = 4W in all) and lane j = t % 16
+// of that group, and holds rows [kR, kR + R) x columns [jC, jC + C) of the
+// tile in VGPRs, so a 16-lane DPP row spans the whole tile width.
+// x-neighbours in other lanes come from DPP row shifts; y-neighbours in other
+// row groups through LDS interface rows, double-buffered so that one barrier
+// per sweep suffices.  The frozen halo sits in registers (columns -1 and TX,
+// in the first / last lane of each DPP row) and in LDS (rows -1 and TY).
+// Used when the grid holds at least one full tile in each direction.
 //
 // Isotropic update in FMA form: fma(S, 1/4, h^2 f / 4) with S = (W + E) +
 // (S + N) equals (h^2 f + S) * 1/4 rounded the two-step way, because scaling
 // by a power of two commutes with rounding; this holds whenever the values
-// involved are normal numbers (magnitudes above 2^-1020 in FP64).
+// involved are normal numbers (magnitudes above 2^-1020 in FP64, 2^-124 in
+// FP32).
 // ============================================================================
 constexpr int kDppRowShr1 = 0x111;  // lane i <- lane i - 1 of its 16-lane row
 constexpr int kDppRowShl1 = 0x101;  // lane i <- lane i + 1 of its 16-lane row
@@ -214,108 +212,23 @@ __device__ __forceinline__ float fma_quarter(float sv, float b)
     return r;
 }
 
-template <typename T, int C, int R, bool RES, bool ISO>
-struct RegTile {
-    static constexpr int TX = 16 * C, TY = 4 * R, NS = R + 1;
-    T xs[NS][C];   // rows in rotating slots
-    T b[R][C];     // f on load; then h^2 f / 4 (iso) or f (general)
-    T up[C], dn[C];
-    const T *phw;  // W halo of the lane's rows (first lane of a DPP row) or zeros
-    const T *phe;  // E halo (last lane) or zeros
-    double rsq;
-
-    // exchange the lane's first / last rows through LDS; up / dn receive the
-    // neighbouring row groups' rows (or the frozen halo rows for groups 0 / 3)
-    template <int P>
-    __device__ __forceinline__ void exchange(T (*s_top)[TX], T (*s_bot)[TX], const T *pu,
-                                             const T *pd, int k, int lc0)
-    {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            s_top[k][lc0 + c] = xs[(0 + P) % NS][c];
-            s_bot[k][lc0 + c] = xs[(R - 1 + P) % NS][c];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            up[c] = pu[c];
-            dn[c] = pd[c];
-        }
-        __syncthreads();  // every lane has read before the next exchange writes
-    }
-
-    // one sub-iteration at phase P; FIRST also forms the residual of the
-    // incoming iterate over the owned points and scales f
-    template <int P, bool FIRST>
-    __device__ __forceinline__ void sweep(T hh, T wx, T wy, T dinv, double gwx, double gwy, int rlo,
-                                          int rhi, int clo, int chi)
-    {
-        T above[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) above[c] = up[c];
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const int cur = (i + P) % NS;
-            const int dst = (i + P + R) % NS;  // slot of the old row i - 1
-            const T wl = dpp_shift<kDppRowShr1>(xs[cur][C - 1]);
-            const T er = dpp_shift<kDppRowShl1>(xs[cur][0]);
-            const T hwi = phw[i], hei = phe[i];
-            T nw[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const T w = c > 0 ? xs[cur][c - 1] : wl;
-                const T e = c < C - 1 ? xs[cur][c + 1] : er;
-                T we = w + e;
-                // the halo values are 0 except in the first / last lane of a
-                // DPP row, where the shifted value is 0: the sum stays W + E
-                if (c == 0) we = we + hwi;
-                if (c == C - 1) we = we + hei;
-                const T below = i < R - 1 ? xs[(i + 1 + P) % NS][c] : dn[c];
-                const T sn = above[c] + below;
-                if (FIRST) {
-                    if (RES && i >= rlo && i < rhi && c >= clo && c < chi) {
-                        const double wa = c > 0 ? (double)w : (double)wl + (double)hwi;
-                        const double ea = c < C - 1 ? (double)e : (double)er + (double)hei;
-                        const double xc = (double)xs[cur][c];
-                        const double rr = (double)b[i][c] -
-                                          (gwx * ((2.0 * xc - wa) - ea) +
-                                           gwy * ((2.0 * xc - (double)above[c]) - (double)below));
-                        rsq += rr * rr;
-                    }
-                    if (ISO) b[i][c] = (hh * b[i][c]) * T(0.25);
-                }
-                if (ISO) nw[c] = fma_quarter(we + sn, b[i][c]);
-                else nw[c] = (b[i][c] + (wx * we + wy * sn)) * dinv;
-            }
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                above[c] = xs[cur][c];
-                xs[dst][c] = nw[c];
-            }
-        }
-    }
-};
-
-template <typename T, int C, int R, bool RES, bool ISO>
-__global__ __launch_bounds__(64) void k_cycle2d_reg(Geom2 g, const T *__restrict__ f,
-                                                    const T *__restrict__ xin,
-                                                    T *__restrict__ xout, int nsub, Red red,
-                                                    double tol)
+template <typename T, int C, int R, int W, bool RES, bool ISO>
+__global__ __launch_bounds__(64 * W) void k_cycle2d_reg(Geom2 g, const T *__restrict__ f,
+                                                        const T *__restrict__ xin,
+                                                        T *__restrict__ xout, int nsub, Red red,
+                                                        double tol)
 {
-    using Tile = RegTile<T, C, R, RES, ISO>;
-    constexpr int TX = Tile::TX, TY = Tile::TY, NS = Tile::NS;
+    constexpr int TX = 16 * C, TY = 4 * R * W, NG = 4 * W, NT = 64 * W;
     if (RES) {
         if (read_status(red.ctrl) != ST_RUNNING) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
-            judge_partials<64>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
+            judge_partials<NT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
-    __shared__ T s_top[4][TX];   // first row of each row group (current sweep)
-    __shared__ T s_bot[4][TX];   // last row of each row group
-    __shared__ T s_halo[2][TX];  // frozen rows -1 and TY
-    __shared__ T s_hwe[2][TY];   // frozen columns -1 and TX
-    __shared__ T s_zero[R];
+    __shared__ T s_top[2][NG][TX];  // first row of each row group, by sweep parity
+    __shared__ T s_bot[2][NG][TX];  // last row of each row group
+    __shared__ T s_halo[2][TX];     // frozen rows -1 and TY
 
-    const int lane = threadIdx.x, k = lane >> 4, j = lane & 15;
+    const int k = (int)threadIdx.x >> 4, j = (int)threadIdx.x & 15;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int bi = tile / g.ntx, bj = tile - bi * g.ntx;
     const int r0 = axis_origin(g.ny, TY, g.oy, bi);
@@ -324,28 +237,24 @@ __global__ __launch_bounds__(64) void k_cycle2d_reg(Geom2 g, const T *__restrict
     const int lr0 = k * R, lc0 = j * C;
     const int64_t base = (int64_t)(r0 + lr0) * ld + c0 + lc0;
 
-    // step 1: tile, halo and f into registers / LDS (phase 0: row i in slot i)
-    Tile t;
-    t.rsq = 0.0;
+    // step 1: tile, halo and f into registers / LDS
+    T x[R][C], bq[R][C], hw[R], he[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            t.xs[i][c] = xin[base + (int64_t)i * ld + c];
-            t.b[i][c] = f[base + (int64_t)i * ld + c];
+            x[i][c] = xin[base + (int64_t)i * ld + c];
+            bq[i][c] = f[base + (int64_t)i * ld + c];  // f for now, scaled after the residual
         }
-        if (j == 0) s_hwe[0][lr0 + i] = c0 > 0 ? xin[base + (int64_t)i * ld - 1] : T(0);
-        if (j == 15) s_hwe[1][lr0 + i] = c0 + TX < g.nx ? xin[base + (int64_t)i * ld + C] : T(0);
+        hw[i] = (j == 0 && c0 > 0) ? xin[base + (int64_t)i * ld - 1] : T(0);
+        he[i] = (j == 15 && c0 + TX < g.nx) ? xin[base + (int64_t)i * ld + C] : T(0);
     }
-    if (lane < R) s_zero[lane] = T(0);
-    t.phw = j == 0 ? &s_hwe[0][lr0] : s_zero;
-    t.phe = j == 15 ? &s_hwe[1][lr0] : s_zero;
     if (k == 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
             s_halo[0][lc0 + c] = r0 > 0 ? xin[(int64_t)(r0 - 1) * ld + c0 + lc0 + c] : T(0);
     }
-    if (k == 3) {
+    if (k == NG - 1) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
             s_halo[1][lc0 + c] =
@@ -355,47 +264,93 @@ __global__ __launch_bounds__(64) void k_cycle2d_reg(Geom2 g, const T *__restrict
     const int rhi = axis_own_end(g.ny, TY, g.oy, bi, g.nty) - r0 - lr0;
     const int clo = axis_own_begin(g.nx, TX, g.ox, bj) - c0 - lc0;
     const int chi = axis_own_end(g.nx, TX, g.ox, bj, g.ntx) - c0 - lc0;
-    const T *pu = k == 0 ? &s_halo[0][lc0] : &s_bot[k - 1][lc0];
-    const T *pd = k == 3 ? &s_halo[1][lc0] : &s_top[k + 1][lc0];
-    const T hh = T(g.hh), wx = T(g.wx), wy = T(g.wy), dinv = T(g.dinv);
 
-    // step 2: nsub sub-iterations with the halo frozen.  The first runs at
-    // phase 0; then full rounds of NS sweeps (phases NS-1 .. 0, straight-line
-    // code, so the slot rotation costs no register moves); then the remainder.
-    auto one = [&]<int P>() {
-        t.template exchange<P>(s_top, s_bot, pu, pd, k, lc0);
-        t.template sweep<P, false>(hh, wx, wy, dinv, g.wx, g.wy, rlo, rhi, clo, chi);
+    const T wx = T(g.wx), wy = T(g.wy), dinv = T(g.dinv);
+    T up[C], dn[C];
+    // Publish this group's first / last rows for the sweep of parity par and
+    // fetch the neighbouring groups' (or the frozen halo rows).  A buffer is
+    // rewritten two sweeps later, after a barrier that every thread reaches
+    // only once its reads from it are done.
+    auto exchange = [&](int par) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s_top[par][k][lc0 + c] = x[0][c];
+            s_bot[par][k][lc0 + c] = x[R - 1][c];
+        }
+        __syncthreads();
+        const T *pu = k == 0 ? &s_halo[0][lc0] : &s_bot[par][k - 1][lc0];
+        const T *pd = k == NG - 1 ? &s_halo[1][lc0] : &s_top[par][k + 1][lc0];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            up[c] = pu[c];
+            dn[c] = pd[c];
+        }
     };
-    t.template exchange<0>(s_top, s_bot, pu, pd, k, lc0);
-    t.template sweep<0, true>(hh, wx, wy, dinv, g.wx, g.wy, rlo, rhi, clo, chi);
-    int it = 1;
-    for (; it + NS <= nsub; it += NS) {
-        [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
-            (one.template operator()<NS - 1 - Ps>(), ...);
-        }(std::make_integer_sequence<int, NS>{});
+
+    // One sub-iteration over the lane's rows, top to bottom, in place: prev
+    // keeps the old row above.  FIRST: bq still holds f; it also accumulates
+    // the residual of the incoming iterate over the owned points and scales f
+    // (h^2 f / 4 when isotropic) as it goes.
+    double rsq = 0.0;
+    const T hh = T(g.hh);
+    auto sweep = [&](auto first_tag) {
+        constexpr bool FIRST = decltype(first_tag)::value;
+        T prev[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) prev[c] = up[c];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const T wl = dpp_shift<kDppRowShr1>(x[i][C - 1]);
+            const T er = dpp_shift<kDppRowShl1>(x[i][0]);
+            T nw[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T w = c > 0 ? x[i][c - 1] : wl;
+                const T e = c < C - 1 ? x[i][c + 1] : er;
+                T we = w + e;
+                // the halo registers are 0 except in the first / last lane of a
+                // DPP row, where the shifted value is 0: the sum stays W + E
+                if (c == 0) we = we + hw[i];
+                if (c == C - 1) we = we + he[i];
+                const T below = i < R - 1 ? x[i + 1][c] : dn[c];
+                const T sn = prev[c] + below;
+                if (FIRST) {
+                    if (RES && i >= rlo && i < rhi && c >= clo && c < chi) {
+                        const double wa = c > 0 ? (double)w : (double)wl + (double)hw[i];
+                        const double ea = c < C - 1 ? (double)e : (double)er + (double)he[i];
+                        const double rr = res2((double)bq[i][c], (double)x[i][c], wa, ea,
+                                               (double)prev[c], (double)below, g.wx, g.wy);
+                        rsq += rr * rr;
+                    }
+                    if (ISO) bq[i][c] = (hh * bq[i][c]) * T(0.25);
+                }
+                if (ISO) nw[c] = fma_quarter(we + sn, bq[i][c]);
+                else nw[c] = (bq[i][c] + (wx * we + wy * sn)) * dinv;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                prev[c] = x[i][c];
+                x[i][c] = nw[c];
+            }
+        }
+    };
+
+    // step 2: nsub sub-iterations with the halo frozen
+    exchange(0);
+    sweep(std::true_type{});
+    for (int it = 1; it < nsub; ++it) {
+        exchange(it & 1);
+        sweep(std::false_type{});
     }
-    const int rem = nsub - it;  // 0 <= rem < NS sweeps left, starting at phase NS - 1
-    [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
-        ((rem > Ps ? (one.template operator()<NS - 1 - Ps>(), 0) : 0), ...);
-    }(std::make_integer_sequence<int, NS - 1>{});
-    // the first sweep leaves phase NS - 1, full rounds return to it, and each
-    // remainder sweep lowers it by one
-    const int ph = NS - 1 - rem;
 
-    // step 3: owned points back to global memory (row i in slot (i + ph) mod NS)
-    [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
-        ((ph == Ps ? ([&] {
+    // step 3: owned points back to global memory
 #pragma unroll
-              for (int i = 0; i < R; ++i)
+    for (int i = 0; i < R; ++i)
 #pragma unroll
-                  for (int c = 0; c < C; ++c)
-                      if (i >= rlo && i < rhi && c >= clo && c < chi)
-                          xout[base + (int64_t)i * ld + c] = t.xs[(i + Ps) % NS][c];
-          }(), 0) : 0),
-         ...);
-    }(std::make_integer_sequence<int, NS>{});
+        for (int c = 0; c < C; ++c)
+            if (i >= rlo && i < rhi && c >= clo && c < chi) xout[base + (int64_t)i * ld + c] = x[i][c];
 
-    if (RES) post_partial<64>(t.rsq, red.part_cur);
+    if (RES) post_partial<NT>(rsq, red.part_cur);
 }
 
 // ============================================================================
@@ -591,20 +546,41 @@ __global__ __launch_bounds__(kNT) void k_judge(const double *part, int n, Ctrl *
 }
 
 // ---------------------------------------------------------------- dispatch
-template <typename T, int C, int R>
+// Register-resident shape for a TX x TY tile: C columns and R rows per lane,
+// W wavefronts.  Up to 32 x 32 one wavefront holds the tile (R = TY / 4);
+// taller tiles use 4 rows per lane (8 at TX = 32) and more wavefronts, which
+// keeps the per-lane footprint small enough for three or more waves per SIMD.
+template <int TX, int TY>
+struct RegShape {
+    static constexpr int C = TX / 16;
+    static constexpr int R = (TX <= 64 && TY <= 32) ? TY / 4 : (TX == 32 ? 8 : 4);
+    static constexpr int W = TY / (4 * R);
+    static constexpr bool ok = (TX == 32 || TX == 64 || TX == 128) && TY >= 16 && TY <= 128 &&
+                               W >= 1 && 4 * R * W == TY;
+};
+
+// shapes the LDS kernel provides (full or partial tiles)
+constexpr bool lds_shape(int tx, int ty)
+{
+    return (tx == 16 || tx == 32 || tx == 64) && (ty == 16 || ty == 32 || ty == 64);
+}
+
+template <typename T, int TX, int TY>
 hipError_t cyc2_reg(const Geom2 &g, int s, bool res, const void *f, const void *xin, void *xout,
                     const Red &red, double tol, hipStream_t st)
 {
+    using S = RegShape<TX, TY>;
+    constexpr int C = S::C, R = S::R, W = S::W;
     const unsigned nb = (unsigned)((int64_t)g.ntx * g.nty);
     const T *F = (const T *)f;
     const T *XI = (const T *)xin;
     T *XO = (T *)xout;
     if (res) {
-        if (g.iso) k_cycle2d_reg<T, C, R, true, true><<<nb, 64, 0, st>>>(g, F, XI, XO, s, red, tol);
-        else k_cycle2d_reg<T, C, R, true, false><<<nb, 64, 0, st>>>(g, F, XI, XO, s, red, tol);
+        if (g.iso) k_cycle2d_reg<T, C, R, W, true, true><<<nb, 64 * W, 0, st>>>(g, F, XI, XO, s, red, tol);
+        else k_cycle2d_reg<T, C, R, W, true, false><<<nb, 64 * W, 0, st>>>(g, F, XI, XO, s, red, tol);
     } else {
-        if (g.iso) k_cycle2d_reg<T, C, R, false, true><<<nb, 64, 0, st>>>(g, F, XI, XO, s, red, tol);
-        else k_cycle2d_reg<T, C, R, false, false><<<nb, 64, 0, st>>>(g, F, XI, XO, s, red, tol);
+        if (g.iso) k_cycle2d_reg<T, C, R, W, false, true><<<nb, 64 * W, 0, st>>>(g, F, XI, XO, s, red, tol);
+        else k_cycle2d_reg<T, C, R, W, false, false><<<nb, 64 * W, 0, st>>>(g, F, XI, XO, s, red, tol);
     }
     return hipGetLastError();
 }
@@ -613,24 +589,32 @@ template <typename T, int TX, int TY>
 hipError_t cyc2(const Geom2 &g, int s, bool res, const void *f, const void *xin, void *xout,
                 const Red &red, double tol, hipStream_t st)
 {
-    // full tiles of a register-resident shape: one wavefront per tile
-    if (g.reg && g.nx >= TX && g.ny >= TY) {
-        if constexpr ((TX == 32 || TX == 64) && (TY == 16 || TY == 32))
-            return cyc2_reg<T, TX / 16, TY / 4>(g, s, res, f, xin, xout, red, tol, st);
+    if constexpr (RegShape<TX, TY>::ok) {
+        if (g.reg && g.nx >= TX && g.ny >= TY)
+            return cyc2_reg<T, TX, TY>(g, s, res, f, xin, xout, red, tol, st);
     }
-    const unsigned nb = (unsigned)((int64_t)g.ntx * g.nty);
-    const T *F = (const T *)f;
-    const T *XI = (const T *)xin;
-    T *XO = (T *)xout;
-    if (res) {
-        if (g.iso) k_cycle2d<T, TX, TY, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
-        else k_cycle2d<T, TX, TY, true, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
-    } else {
-        if (g.iso) k_cycle2d<T, TX, TY, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
-        else k_cycle2d<T, TX, TY, false, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
+    if constexpr (lds_shape(TX, TY)) {
+        const unsigned nb = (unsigned)((int64_t)g.ntx * g.nty);
+        const T *F = (const T *)f;
+        const T *XI = (const T *)xin;
+        T *XO = (T *)xout;
+        if (res) {
+            if (g.iso) k_cycle2d<T, TX, TY, true, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
+            else k_cycle2d<T, TX, TY, true, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
+        } else {
+            if (g.iso) k_cycle2d<T, TX, TY, false, true><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
+            else k_cycle2d<T, TX, TY, false, false><<<nb, kNT, 0, st>>>(g, F, XI, XO, s, red, tol);
+        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;  // excluded beforehand by cycle2d_runnable
 }
+
+#define HJ_TILES(X)                                                                       \
+    X(16, 16) X(16, 32) X(16, 64)                                                         \
+    X(32, 16) X(32, 32) X(32, 64) X(32, 128)                                              \
+    X(64, 16) X(64, 32) X(64, 64) X(64, 128)                                              \
+    X(128, 16) X(128, 32) X(128, 64) X(128, 128)
 
 template <typename T>
 hipError_t cyc2_t(const Geom2 &g, int s, bool res, const void *f, const void *xin, void *xout,
@@ -638,9 +622,7 @@ hipError_t cyc2_t(const Geom2 &g, int s, bool res, const void *f, const void *xi
 {
 #define HJ_TILE(a, b)                                                                     \
     if (g.tx == a && g.ty == b) return cyc2<T, a, b>(g, s, res, f, xin, xout, red, tol, st);
-    HJ_TILE(16, 16) HJ_TILE(16, 32) HJ_TILE(16, 64)
-    HJ_TILE(32, 16) HJ_TILE(32, 32) HJ_TILE(32, 64)
-    HJ_TILE(64, 16) HJ_TILE(64, 32) HJ_TILE(64, 64)
+    HJ_TILES(HJ_TILE)
 #undef HJ_TILE
     return hipErrorInvalidValue;
 }
@@ -675,8 +657,17 @@ hipError_t cyc1_t(const Geom1 &g, int s, bool res, const void *f, const void *xi
 
 bool cycle2d_supported(int tx, int ty)
 {
-    auto ok = [](int v) { return v == 16 || v == 32 || v == 64; };
-    return ok(tx) && ok(ty);
+#define HJ_TILE(a, b) if (tx == a && ty == b) return true;
+    HJ_TILES(HJ_TILE)
+#undef HJ_TILE
+    return false;
+}
+
+bool cycle2d_runnable(const Geom2 &g)
+{
+    if (lds_shape(g.tx, g.ty)) return true;
+    // tiles with a 128 extent exist only register-resident, for full tiles
+    return g.reg && g.nx >= g.tx && g.ny >= g.ty;
 }
 
 bool cycle1d_supported(int t)

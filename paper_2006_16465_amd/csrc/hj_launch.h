@@ -31,6 +31,9 @@ struct Geom1 {
 };
 
 bool cycle2d_supported(int tx, int ty);
+// false when the tile shape has no kernel for this grid (a 128 extent needs
+// the register kernel and a grid of at least one full tile)
+bool cycle2d_runnable(const Geom2 &g);
 bool cycle1d_supported(int t);
 
 // Number of workgroups (= reduction partials) each launcher uses.

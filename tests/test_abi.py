@@ -59,7 +59,12 @@ FAKE = 0x10000  # aligned non-NULL pointer; validation must reject before it is 
     ((8, 8, 8, 0.1, 0.1, 0), {"flags": 2}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"rel_tol": float("nan")}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"tile_x": 48}, hj.HJ_ERR_UNSUPPORTED),
-    ((8, 8, 8, 0.1, 0.1, 0), {"tile_y": 128}, hj.HJ_ERR_UNSUPPORTED),
+    ((8, 8, 8, 0.1, 0.1, 0), {"tile_x": 16, "tile_y": 128}, hj.HJ_ERR_UNSUPPORTED),
+    ((8, 8, 8, 0.1, 0.1, 0), {"tile_y": 256}, hj.HJ_ERR_UNSUPPORTED),
+    # 128-extent tiles only on grids of at least one full tile, register kernel only
+    ((100, 200, 100, 0.1, 0.1, 0), {"tile_x": 128, "tile_y": 64}, hj.HJ_ERR_UNSUPPORTED),
+    ((200, 100, 200, 0.1, 0.1, 0), {"tile_x": 64, "tile_y": 128}, hj.HJ_ERR_UNSUPPORTED),
+    ((256, 256, 256, 0.1, 0.1, 0), {"tile_x": 128, "tile_y": 128, "flags": 1}, hj.HJ_ERR_UNSUPPORTED),
 ])
 def test_solve_2d_rejects_invalid_arguments(args, kw, code):
     lib = hj.load()

@@ -120,6 +120,61 @@ def test_register_and_lds_kernels_match_oracle(orc, tile, overlap):
         assert np.array_equal(got_lds, want), "LDS kernel"
 
 
+@pytest.mark.parametrize("tile", [(32, 64), (32, 128), (64, 64), (64, 128), (128, 16), (128, 32),
+                                  (128, 64), (128, 128)])
+@pytest.mark.parametrize("overlap", [(0, 0), (14, 14), (30, 6)])
+def test_multiwave_register_kernel_matches_oracle(orc, tile, overlap):
+    """Tiles held by several wavefronts (or 128 columns wide): ragged grids of a
+    few tiles per axis, with and without overlap, FP64 bit for bit."""
+    ny, nx = 300, 270
+    ov = (min(overlap[0], tile[0] - 2), min(overlap[1], tile[1] - 2))
+    f = W.rhs_random((ny, nx), tile[0] * 7 + tile[1] + ov[0])
+    x0 = W.rhs_random((ny, nx), 11 + ov[1])
+    h = 1.0 / 301
+    for s, nc in ((1, 2), (3, 3), (8, 2)):
+        say(f"multiwave tile={tile} ov={ov} s={s} nc={nc}")
+        got, _ = gpu_cycles_2d(f, x0, h, tile, s, nc, ov)
+        assert np.array_equal(got, orc.hier_2d(f, x0, h, h, tile, s, nc, ov))
+
+
+@pytest.mark.parametrize("tile", [(64, 64), (64, 128), (128, 64)])
+def test_multiwave_register_kernel_aniso_fp32_and_exact_grid(orc, tile):
+    # anisotropic spacing (general update), FP32 within 1e-5, and a grid of
+    # exactly one tile (every halo is the Dirichlet boundary)
+    ny, nx = 200, 260
+    f = W.rhs_random((ny, nx), 3)
+    x0 = W.rhs_random((ny, nx), 4)
+    got, _ = gpu_cycles_2d(f, x0, 1.0 / 261, tile, 6, 3, (10, 10), hy=1.0 / 151)
+    assert np.array_equal(got, orc.hier_2d(f, x0, 1.0 / 261, 1.0 / 151, tile, 6, 3, (10, 10)))
+    g32, _ = gpu_cycles_2d(f, x0, 1.0 / 261, tile, 8, 20, (14, 14), dtype=torch.float32)
+    assert rel(g32, orc.hier_2d(f, x0, 1.0 / 261, 1.0 / 261, tile, 8, 20, (14, 14))) <= 1e-5
+    ty, tx = tile[1], tile[0]
+    f1 = W.rhs_random((ty, tx), 5)
+    got, _ = gpu_cycles_2d(f1, np.zeros_like(f1), 1.0 / (tx + 1), tile, 16, 2)
+    assert np.array_equal(got, orc.hier_2d(f1, np.zeros_like(f1), 1.0 / (tx + 1), 1.0 / (tx + 1), tile, 16, 2))
+
+
+def test_multiwave_solve_to_tolerance_matches_oracle(orc):
+    f = W.rhs_2d_modes(512, 512, 16, 0.1, 6)
+    h = 1.0 / 513
+    X = dev(np.zeros_like(f))
+    info = hj.solve_2d(dev(f), X, h, tile=(64, 128), s=8, overlap=(14, 14), rel_tol=1e-6)
+    xo, co, relo, _ = orc.solve_2d(f, np.zeros_like(f), h, h, tile=(64, 128), s=8, overlap=(14, 14),
+                                   tol=1e-6)
+    say(f"multiwave solve 512^2: gpu cycles {info.cycles}, oracle {co}")
+    assert info.cycles == co
+    assert np.array_equal(host(X), xo)
+    assert abs(info.rel_residual - relo) <= 1e-12 * relo
+
+
+def test_128_tiles_need_full_grid():
+    f = np.zeros((100, 300))
+    with pytest.raises(hj.HJError):
+        gpu_cycles_2d(f, f, 0.01, (64, 128), 4, 1)
+    with pytest.raises(hj.HJError):
+        gpu_cycles_2d(np.zeros((300, 300)), np.zeros((300, 300)), 0.01, (128, 128), 4, 1, lds_kernel=True)
+
+
 @pytest.mark.parametrize("tile", [(32, 32), (64, 32)])
 def test_register_kernel_solve_and_fp32(orc, tile):
     f = W.rhs_2d_modes(256, 256, 16, 0.1, 4)
@@ -277,19 +332,20 @@ def test_4096_time_to_tolerance_workload_matches_oracle(orc):
     assert np.array_equal(host(X0), xo0)
 
 
-def test_4096_benchmark_setting_matches_oracle(orc):
-    """The benchmark's default setting (64 x 32 tiles, s = 8, overlap 14) on the
-    4096^2 workload: fixed cycles and the solve to 1e-6 against the oracle."""
+@pytest.mark.parametrize("tile,s,ov", [((64, 128), 12, (22, 22)), ((64, 32), 8, (14, 14))])
+def test_4096_benchmark_setting_matches_oracle(orc, tile, s, ov):
+    """The benchmark's default setting (64 x 128 tiles, s = 12, overlap 22) and
+    the earlier 64 x 32 one on the 4096^2 workload: fixed cycles and the solve
+    to 1e-6 against the oracle."""
     f, h = W.make("poisson2d_4096", 2)
     x0 = np.zeros_like(f)
-    say("4096^2 fixed 2 cycles T=64x32 s=8 o=14")
-    got, _ = gpu_cycles_2d(f, x0, h, (64, 32), 8, 2, (14, 14))
-    assert np.array_equal(got, orc.hier_2d(f, x0, h, h, (64, 32), 8, 2, (14, 14)))
+    say(f"4096^2 fixed 2 cycles T={tile} s={s} o={ov}")
+    got, _ = gpu_cycles_2d(f, x0, h, tile, s, 2, ov)
+    assert np.array_equal(got, orc.hier_2d(f, x0, h, h, tile, s, 2, ov))
     X = dev(x0)
-    say("4096^2 solve to 1e-6, T=64x32 s=8 o=14")
-    info = hj.solve_2d(dev(f), X, h, tile=(64, 32), s=8, overlap=(14, 14), rel_tol=1e-6)
-    xo, co, relo, _ = orc.solve_2d(f, x0, h, h, tile=(64, 32), s=8, overlap=(14, 14), tol=1e-6,
-                                   max_cycles=1000)
+    say(f"4096^2 solve to 1e-6, T={tile} s={s} o={ov}")
+    info = hj.solve_2d(dev(f), X, h, tile=tile, s=s, overlap=ov, rel_tol=1e-6)
+    xo, co, relo, _ = orc.solve_2d(f, x0, h, h, tile=tile, s=s, overlap=ov, tol=1e-6, max_cycles=1000)
     assert info.cycles == co
     assert np.array_equal(host(X), xo)
     assert abs(info.rel_residual - relo) <= 1e-12 * relo
