@@ -93,7 +93,9 @@ typedef enum hj_method { HJ_HIERARCHICAL = 0, HJ_GLOBAL = 1 } hj_method;
 
 typedef struct hj_params {
     int32_t tile_x;      /* interior tile extent along x (1D: the tile); 0 = 32.
-                            2D supports 16, 32, 64; 1D supports 32..1024 (powers of 2) */
+                            2D supports 16, 32, 64, 128 (x 16, 32, 64, 128; tile_x = 16
+                            only with tile_y <= 64; a 128 extent needs a grid of at
+                            least one full tile); 1D supports 32..1024 (powers of 2) */
     int32_t tile_y;      /* interior tile extent along y (2D); 0 = 32 */
     int32_t overlap_x;   /* interior points shared by x-neighbour tiles, 0 <= o < tile */
     int32_t overlap_y;   /* same along y */
@@ -178,10 +180,59 @@ hj_status hj_residual(int32_t dim, int64_t nx, int64_t ny, int64_t ld, double hx
                       hj_dtype dtype, const void *f, const void *x, void *r_out,
                       double *norm2_out, void *stream);
 
-/* Many independent problems in one launch.  Declared for a later version;
- * returns HJ_ERR_UNSUPPORTED. */
-hj_status hj_solve_batched(const void *desc, int64_t nprob, const hj_params *p, void *stream,
-                           void *infos);
+/* ---------------------------------------------------------------- batches
+ * Many independent problems, 2D and 1D, of uneven sizes, solved together:
+ * every cycle is one launch over the tiles of all 2D problems (two when some
+ * have hx != hy), one over the tile groups of all 1D problems, and one that
+ * judges every problem; a fixed run of such cycles is captured once in a HIP
+ * graph and replayed until every problem has stopped.  Each problem's iterates
+ * equal those of its own hj_solve_2d / hj_solve_1d call with the same cycle
+ * shape, bit for bit, and it stops at its own first cycle that meets rel_tol. */
+typedef struct hj_problem {
+    int32_t dim;        /* 1 or 2 */
+    int32_t flags;      /* must be 0 */
+    int64_t nx, ny, ld; /* 2D: ny rows of ld >= nx elements; 1D: n = nx (ny, ld ignored) */
+    double hx, hy;      /* grid spacings (1D: hx), finite and > 0 */
+    const void *f;      /* device pointer, the batch's dtype */
+    void *x;            /* device pointer, in/out: x_0 in, the stopping iterate out */
+} hj_problem;
+
+#define HJ_BATCH_AUTOTUNE 0x1
+
+typedef struct hj_batch_params {
+    hj_params p2;         /* 2D cycle: tile_x in {32, 64}, tile_y in {16, 32, 64, 128},
+                             overlap, s (register-resident tiles: every 2D problem needs
+                             nx >= tile_x and ny >= tile_y); method HJ_HIERARCHICAL */
+    hj_params p1;         /* 1D cycle: tile_x in 32..1024, overlap_x, s */
+    double rel_tol;       /* per problem; <= 0: every problem runs exactly max_cycles cycles */
+    int64_t max_cycles;   /* >= 1 */
+    int32_t dtype;        /* hj_dtype of every f and x */
+    int32_t graph_cycles; /* cycles per graph replay, 0 = 8, at most 1024 */
+    int32_t flags;        /* 0 or HJ_BATCH_AUTOTUNE: choose p2 and p1 with hj_autotune
+                             (2D on the largest 2D problem, tiles limited to the smallest) */
+    int32_t pad;
+} hj_batch_params;
+
+/* Scratch: one iterate array per problem (the sum of the problems' sizes),
+ * partials and control blocks, kept per device and grown on demand.  infos
+ * (nprob entries) may be NULL.  Returns HJ_OK when every problem met rel_tol
+ * (or ran max_cycles in fixed-count mode), HJ_ERR_NOT_CONVERGED if some
+ * stopped at max_cycles (their latest iterate is in x), HJ_ERR_NONFINITE if
+ * some residual became non-finite. */
+hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batch_params *p,
+                           void *stream, hj_info *infos);
+
+/* Autotuner.  With overlap o = 2s - 2 a cycle is exactly s classical sweeps
+ * (no stale halo value reaches an owned point), so every such shape converges
+ * at the same rate per sweep and the fastest is the one with the least time
+ * per cycle divided by s.  Times a few cycles of each candidate -- 2D tiles
+ * 32x32, 64x32, 32x64, 64x64, 32x128, 64x128 no larger than (nx, ny); 1D tiles
+ * 64..1024 no larger than nx; s from 4 to 16 (2D) or 32 (1D) with 2s - 2 at
+ * most the tile minus 2 -- on a scratch problem of the given size and dtype,
+ * and returns the best shape in *best (hierarchical, other fields defaulted)
+ * and its time per sweep in microseconds.  Results are cached per size. */
+hj_status hj_autotune(int32_t dim, int64_t nx, int64_t ny, hj_dtype dtype, void *stream,
+                      hj_params *best, double *us_per_sweep);
 
 /* Variable-coefficient diffusion -div(a grad u) = f on the 2D grid (the
  * general pentadiagonal Jacobi of Sec. 4 with per-point coefficients), for a

@@ -10,7 +10,10 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
+#include <tuple>
+#include <vector>
 #include <string>
 
 #include "hj.h"
@@ -54,6 +57,7 @@ struct DevScratch {
     hj::Ctrl *ctrl = nullptr;
     hj::Ctrl *host = nullptr;  // 2 pinned slots
     hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t tev[2] = {nullptr, nullptr};  // timing events of the autotuner
 };
 
 constexpr int kMaxDev = 64;
@@ -379,6 +383,182 @@ hj_status solve_vc_locked(const hj_vc_problem &pr, const double *f, double *u, c
     return worst;
 }
 
+
+// ---------------------------------------------------------------- batches
+// Per-device scratch of hj_solve_batched: one iterate array per problem in a
+// single arena, the device problem table, work lists, partials, control
+// blocks, the cycle counter, pinned host copies of the control blocks, and a
+// stream to capture the cycle graph on.  Grown on demand, guarded by the
+// device's mutex.
+struct BatchScratch {
+    hipStream_t cap = nullptr;
+    void *arena = nullptr;
+    int64_t arena_bytes = 0;
+    hj::BProb *probs = nullptr;
+    int64_t nprobs = 0;
+    int32_t *owner = nullptr;
+    int64_t nowner = 0;
+    double *part = nullptr;
+    int64_t npart = 0;
+    hj::Ctrl *ctrl = nullptr;
+    int64_t nctrl = 0;
+    hj::Ctrl *host = nullptr;  // 2 x nhost pinned
+    int64_t nhost = 0;
+    hj::BCtl *bc = nullptr;
+};
+
+BatchScratch g_bat[kMaxDev];
+
+template <typename T>
+hj_status grow_dev(T *&ptr, int64_t &have, int64_t need)
+{
+    if (need <= have) return HJ_OK;
+    if (ptr) HJ_HIP(hipFree(ptr));
+    ptr = nullptr;
+    have = 0;
+    HJ_HIP(hipMalloc((void **)&ptr, (size_t)need * sizeof(T)));
+    have = need;
+    return HJ_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+using TuneKey = std::tuple<int, int64_t, int64_t, int, int, int>;  // dim, nx, ny, dtype, tx max, ty max
+std::map<TuneKey, std::pair<hj_params, double>> g_tune[kMaxDev];
+
+// Time one cycle shape on a zero problem (values do not change the timing:
+// no subnormals arise).  Returns microseconds per cycle, or a negative value
+// when the shape cannot run on this grid.
+hj_status time_shape(int dim, int64_t nx, int64_t ny, hj_dtype dt, const hj_params &P, void *f,
+                     void *xa, void *xb, hipStream_t st, DevScratch &S, double &us)
+{
+    const int idt = dt == HJ_F64 ? hj::F64 : hj::F32;
+    const hj::Red none{nullptr, nullptr, S.ctrl, 0, 0};
+    const double h = 1.0 / (double)(nx + 1);
+    hj::Geom2 g2{};
+    hj::Geom1 g1{};
+    if (dim == 2) {
+        g2 = make_geom2(nx, ny, nx, h, h, P);
+        if (!g2.reg || nx < g2.tx || ny < g2.ty) {
+            us = -1.0;
+            return HJ_OK;
+        }
+    } else {
+        g1 = make_geom1(nx, h, &P);
+    }
+    auto run = [&](int k) -> hipError_t {
+        for (int i = 0; i < k; ++i) {
+            const void *src = (i & 1) ? xb : xa;
+            void *dst = (i & 1) ? xa : xb;
+            const hipError_t e = dim == 2 ? hj::launch_cycle2d(idt, g2, P.s, false, f, src, dst, none, -1.0, st)
+                                          : hj::launch_cycle1d(idt, g1, P.s, false, f, src, dst, none, -1.0, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    HJ_HIP(run(1));  // warm-up
+    int k = 2;
+    for (int pass = 0; pass < 2; ++pass) {
+        HJ_HIP(hipEventRecord(S.tev[0], st));
+        HJ_HIP(run(k));
+        HJ_HIP(hipEventRecord(S.tev[1], st));
+        HJ_HIP(hipEventSynchronize(S.tev[1]));
+        float ms = 0.0f;
+        HJ_HIP(hipEventElapsedTime(&ms, S.tev[0], S.tev[1]));
+        us = 1e3 * (double)ms / k;
+        // second pass long enough to average out launch jitter (about 1 ms)
+        k = (int)std::min(64.0, std::max(3.0, 1000.0 / std::max(us, 1.0)));
+    }
+    return HJ_OK;
+}
+
+hj_status autotune_locked(int dim, int64_t nx, int64_t ny, hj_dtype dt, int txmax, int tymax,
+                          hipStream_t st, int dev, DevScratch &S, hj_params &best, double &best_us)
+{
+    const TuneKey key{dim, nx, ny, (int)dt, txmax, tymax};
+    auto it = g_tune[dev].find(key);
+    if (it != g_tune[dev].end()) {
+        best = it->second.first;
+        best_us = it->second.second;
+        return HJ_OK;
+    }
+    const int64_t npts = dim == 2 ? nx * ny : nx;
+    const size_t bytes = (size_t)npts * esize(dt);
+    hj_status r;
+    if ((r = scratch_ensure(S, 3 * bytes, 2)) != HJ_OK) return r;
+    if (!S.tev[0]) {
+        HJ_HIP(hipEventCreate(&S.tev[0]));
+        HJ_HIP(hipEventCreate(&S.tev[1]));
+    }
+    char *base = (char *)S.xbuf;
+    HJ_HIP(hipMemsetAsync(base, 0, 3 * bytes, st));
+    void *f = base, *xa = base + bytes, *xb = base + 2 * bytes;
+
+    std::vector<hj_params> cands;
+    auto add = [&](int tx, int ty, int s) {
+        hj_params P;
+        hj_params_default(&P);
+        P.tile_x = tx;
+        P.tile_y = dim == 2 ? ty : 0;
+        P.s = s;
+        P.overlap_x = 2 * s - 2;
+        P.overlap_y = dim == 2 ? 2 * s - 2 : 0;
+        cands.push_back(P);
+    };
+    if (dim == 2) {
+        const int shapes[][2] = {{32, 32}, {64, 32}, {32, 64}, {64, 64}, {32, 128}, {64, 128}};
+        for (auto &sh : shapes) {
+            if (sh[0] > txmax || sh[1] > tymax || sh[0] > nx || sh[1] > ny) continue;
+            for (int s : {4, 6, 8, 10, 12, 16})
+                if (2 * s - 2 <= std::min(sh[0], sh[1]) - 2) add(sh[0], sh[1], s);
+        }
+    } else {
+        for (int t : {64, 128, 256, 512, 1024}) {
+            if (t > txmax || (t > nx && t != 64)) continue;
+            for (int s : {4, 8, 12, 16, 24, 32})
+                if (2 * s - 2 <= t - 2) add(t, 0, s);
+        }
+    }
+    if (cands.empty())
+        return fail(HJ_ERR_UNSUPPORTED, dim == 2 ? "autotune: the grid is smaller than a 32 x 32 tile"
+                                                 : "autotune: no 1D tile fits");
+    best_us = INFINITY;
+    for (const hj_params &P : cands) {
+        double us = 0.0;
+        if ((r = time_shape(dim, nx, ny, dt, P, f, xa, xb, st, S, us)) != HJ_OK) return r;
+        if (us <= 0.0) continue;
+        const double per_sweep = us / P.s;
+        if (per_sweep < best_us) {
+            best_us = per_sweep;
+            best = P;
+        }
+    }
+    if (!std::isfinite(best_us)) return fail(HJ_ERR_UNSUPPORTED, "autotune: no candidate runs on this grid");
+    g_tune[dev][key] = {best, best_us};
+    return HJ_OK;
+}
+
+hj_status check_problem(const hj_problem &q, hj_dtype dt, int dev, int64_t i)
+{
+    const std::string at = "problem " + std::to_string(i) + ": ";
+    if (q.flags != 0) return fail(HJ_ERR_INVALID_ARG, at + "flags must be 0");
+    if (q.dim != 1 && q.dim != 2) return fail(HJ_ERR_INVALID_ARG, at + "dim must be 1 or 2");
+    if (q.nx < 1 || q.nx > kMaxAxis) return fail(HJ_ERR_INVALID_ARG, at + "nx must be in [1, 2^30]");
+    if (!finite_pos(q.hx)) return fail(HJ_ERR_INVALID_ARG, at + "hx must be finite and > 0");
+    if (q.dim == 2) {
+        if (q.ny < 1 || q.ny > kMaxAxis) return fail(HJ_ERR_INVALID_ARG, at + "ny must be in [1, 2^30]");
+        if (q.ld < q.nx) return fail(HJ_ERR_INVALID_ARG, at + "ld must be >= nx");
+        if (!finite_pos(q.hy)) return fail(HJ_ERR_INVALID_ARG, at + "hy must be finite and > 0");
+    }
+    hj_status r;
+    if ((r = check_ptr_dtype(q.f, dt, (at + "f").c_str(), false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(q.x, dt, (at + "x").c_str(), false)) != HJ_OK) return r;
+    if (dev >= 0) {
+        if ((r = check_device_ptr(q.f, dev, (at + "f").c_str())) != HJ_OK) return r;
+        if ((r = check_device_ptr(q.x, dev, (at + "x").c_str())) != HJ_OK) return r;
+    }
+    return HJ_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -692,9 +872,260 @@ hj_status hj_residual(int32_t dim, int64_t nx, int64_t ny, int64_t ld, double hx
     return HJ_OK;
 }
 
-hj_status hj_solve_batched(const void *, int64_t, const hj_params *, void *, void *)
+hj_status hj_autotune(int32_t dim, int64_t nx, int64_t ny, hj_dtype dtype, void *stream,
+                      hj_params *best, double *us_per_sweep)
 {
-    return fail(HJ_ERR_UNSUPPORTED, "hj_solve_batched is not provided by this version");
+    g_err.clear();
+    if (dim != 1 && dim != 2) return fail(HJ_ERR_INVALID_ARG, "dim must be 1 or 2");
+    if (nx < 1 || nx > kMaxAxis || (dim == 2 && (ny < 1 || ny > kMaxAxis)))
+        return fail(HJ_ERR_INVALID_ARG, "nx, ny must be in [1, 2^30]");
+    if (dtype != HJ_F64 && dtype != HJ_F32) return fail(HJ_ERR_INVALID_ARG, "unknown dtype");
+    if (!best) return fail(HJ_ERR_INVALID_ARG, "best is NULL");
+    int dev = 0;
+    HJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
+    DevScratch &S = g_scr[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    hj_params P;
+    double us = 0.0;
+    const hj_status r = autotune_locked(dim, nx, dim == 2 ? ny : 1, dtype, 1 << 30, 1 << 30,
+                                        (hipStream_t)stream, dev, S, P, us);
+    if (r != HJ_OK) return r;
+    *best = P;
+    if (us_per_sweep) *us_per_sweep = us;
+    return HJ_OK;
+}
+
+hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batch_params *p,
+                           void *stream, hj_info *infos)
+{
+    g_err.clear();
+    if (!probs) return fail(HJ_ERR_INVALID_ARG, "probs is NULL");
+    if (nprob < 1 || nprob > (1 << 24)) return fail(HJ_ERR_INVALID_ARG, "nprob must be in [1, 2^24]");
+    if (!p) return fail(HJ_ERR_INVALID_ARG, "params is NULL");
+    const hj_dtype dt = (hj_dtype)p->dtype;
+    if (dt != HJ_F64 && dt != HJ_F32) return fail(HJ_ERR_INVALID_ARG, "unknown dtype");
+    if (std::isnan(p->rel_tol)) return fail(HJ_ERR_INVALID_ARG, "rel_tol is NaN");
+    if (p->max_cycles < 1) return fail(HJ_ERR_INVALID_ARG, "max_cycles must be >= 1");
+    if (p->graph_cycles < 0 || p->graph_cycles > 1024)
+        return fail(HJ_ERR_INVALID_ARG, "graph_cycles must be in [0, 1024]");
+    if (p->flags & ~HJ_BATCH_AUTOTUNE) return fail(HJ_ERR_INVALID_ARG, "unknown bits in flags");
+    const bool tune = (p->flags & HJ_BATCH_AUTOTUNE) != 0;
+    hj_status r;
+    int64_t n2 = 0, n1 = 0, min_nx = INT64_MAX, min_ny = INT64_MAX, big2 = -1, big1 = -1;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const hj_problem &q = probs[i];
+        if ((r = check_problem(q, dt, -1, i)) != HJ_OK) return r;
+        if (q.dim == 2) {
+            ++n2;
+            min_nx = std::min(min_nx, q.nx);
+            min_ny = std::min(min_ny, q.ny);
+            if (big2 < 0 || q.nx * q.ny > probs[big2].nx * probs[big2].ny) big2 = i;
+        } else {
+            ++n1;
+            if (big1 < 0 || q.nx > probs[big1].nx) big1 = i;
+        }
+    }
+    if (!tune) {
+        if (n2) {
+            if ((r = check_params(&p->p2, 2)) != HJ_OK) return r;
+            if (p->p2.method != HJ_HIERARCHICAL || p->p2.flags != 0)
+                return fail(HJ_ERR_UNSUPPORTED, "batched 2D cycles are hierarchical, register-resident");
+            if (!hj::batch2d_supported(p->p2.tile_x, p->p2.tile_y))
+                return fail(HJ_ERR_UNSUPPORTED, "batched 2D tiles: tile_x in {32, 64}, tile_y in {16, 32, 64, 128}");
+            if (min_nx < p->p2.tile_x || min_ny < p->p2.tile_y)
+                return fail(HJ_ERR_UNSUPPORTED, "every 2D problem of a batch needs nx >= tile_x and ny >= tile_y");
+        }
+        if (n1) {
+            if ((r = check_params(&p->p1, 1)) != HJ_OK) return r;
+            if (p->p1.method != HJ_HIERARCHICAL)
+                return fail(HJ_ERR_UNSUPPORTED, "batched 1D cycles are hierarchical");
+        }
+    }
+
+    int dev = 0;
+    HJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
+    for (int64_t i = 0; i < nprob; ++i)
+        if ((r = check_problem(probs[i], dt, dev, i)) != HJ_OK) return r;
+
+    DevScratch &S = g_scr[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    hipStream_t st = (hipStream_t)stream;
+    hj_params P2 = p->p2, P1 = p->p1;
+    if (tune) {
+        double us = 0.0;
+        if (n2 && (r = autotune_locked(2, probs[big2].nx, probs[big2].ny, dt, (int)std::min<int64_t>(min_nx, 64),
+                                       (int)std::min<int64_t>(min_ny, 128), st, dev, S, P2, us)) != HJ_OK)
+            return r;
+        if (n1 && (r = autotune_locked(1, probs[big1].nx, 1, dt, 1 << 30, 1 << 30, st, dev, S, P1, us)) != HJ_OK)
+            return r;
+    }
+    const int idt = dt == HJ_F64 ? hj::F64 : hj::F32;
+    const size_t es = esize(dt);
+
+    // host tables: problem records, work lists (iso 2D, other 2D, 1D), arena offsets
+    std::vector<hj::BProb> hp((size_t)nprob);
+    std::vector<int32_t> own_iso, own_gen, own_1d;
+    int64_t arena = 0, npart = 0;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const hj_problem &q = probs[i];
+        hj::BProb &b = hp[(size_t)i];
+        std::memset(&b, 0, sizeof(b));
+        b.dim = q.dim;
+        b.f = q.f;
+        b.x = q.x;
+        int64_t items = 0, elems = 0;
+        std::vector<int32_t> *lst = &own_1d;
+        if (q.dim == 2) {
+            b.g2 = make_geom2(q.nx, q.ny, q.ld, q.hx, q.hy, P2);
+            items = (int64_t)b.g2.ntx * b.g2.nty;
+            elems = q.ny * q.ld;
+            lst = b.g2.iso ? &own_iso : &own_gen;
+        } else {
+            b.g1 = make_geom1(q.nx, q.hx, &P1);
+            items = hj::cycle1d_blocks(b.g1);
+            elems = q.nx;
+        }
+        b.item0 = (int64_t)lst->size();
+        b.nitems = items;
+        b.part0 = npart;
+        npart += items;
+        lst->insert(lst->end(), (size_t)items, (int32_t)i);
+        b.s1 = (void *)(intptr_t)arena;  // offset; rebased below
+        arena += ((int64_t)elems * (int64_t)es + 255) / 256 * 256;
+    }
+    const int64_t nown = (int64_t)(own_iso.size() + own_gen.size() + own_1d.size());
+    if (nown > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "batch too large");
+
+    BatchScratch &B = g_bat[dev];
+    if (!B.cap) HJ_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
+    if (!B.bc) HJ_HIP(hipMalloc((void **)&B.bc, sizeof(hj::BCtl)));
+    if (!S.ev[0]) {
+        if ((r = scratch_ensure(S, 0, 0)) != HJ_OK) return r;
+    }
+    {
+        char *a8 = (char *)B.arena;
+        int64_t have = B.arena_bytes;
+        if ((r = grow_dev(a8, have, arena)) != HJ_OK) return r;
+        B.arena = a8;
+        B.arena_bytes = have;
+    }
+    if ((r = grow_dev(B.probs, B.nprobs, nprob)) != HJ_OK) return r;
+    if ((r = grow_dev(B.owner, B.nowner, std::max<int64_t>(nown, 1))) != HJ_OK) return r;
+    if ((r = grow_dev(B.part, B.npart, 2 * npart)) != HJ_OK) return r;
+    if ((r = grow_dev(B.ctrl, B.nctrl, nprob)) != HJ_OK) return r;
+    if (nprob > B.nhost) {
+        if (B.host) HJ_HIP(hipHostFree(B.host));
+        B.host = nullptr;
+        B.nhost = 0;
+        HJ_HIP(hipHostMalloc((void **)&B.host, (size_t)(2 * nprob) * sizeof(hj::Ctrl), hipHostMallocDefault));
+        B.nhost = nprob;
+    }
+    for (auto &b : hp) b.s1 = (char *)B.arena + (intptr_t)b.s1;
+    std::vector<int32_t> own;
+    own.reserve((size_t)nown);
+    own.insert(own.end(), own_iso.begin(), own_iso.end());
+    own.insert(own.end(), own_gen.begin(), own_gen.end());
+    own.insert(own.end(), own_1d.begin(), own_1d.end());
+    HJ_HIP(hipMemcpyAsync(B.probs, hp.data(), hp.size() * sizeof(hj::BProb), hipMemcpyHostToDevice, st));
+    if (nown) HJ_HIP(hipMemcpyAsync(B.owner, own.data(), own.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    const double tol = p->rel_tol > 0.0 ? p->rel_tol : -1.0;
+    HJ_HIP(hj::launch_batch_init(B.ctrl, (int)nprob, B.bc, p->max_cycles, tol, st));
+    HJ_HIP(hipStreamSynchronize(st));  // host tables may go out of scope after this
+
+    // capture a fixed run of cycles; the cycle index lives on the device
+    const int K = p->graph_cycles ? p->graph_cycles : 8;
+    const hj::BatchLaunch Li{B.probs, B.owner, (int64_t)own_iso.size(), B.bc, B.ctrl, B.part, npart, P2.s};
+    const hj::BatchLaunch Lg{B.probs, B.owner + own_iso.size(), (int64_t)own_gen.size(), B.bc, B.ctrl,
+                             B.part, npart, P2.s};
+    const hj::BatchLaunch L1{B.probs, B.owner + own_iso.size() + own_gen.size(), (int64_t)own_1d.size(),
+                             B.bc, B.ctrl, B.part, npart, P1.s};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HJ_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (int k = 0; k < K && ce == hipSuccess; ++k) {
+        if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, true, Li, B.cap);
+        if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, false, Lg, B.cap);
+        if (ce == hipSuccess) ce = hj::launch_batch_cycle1d(idt, P1.tile_x, L1, B.cap);
+        if (ce == hipSuccess) ce = hj::launch_batch_judge(B.probs, (int)nprob, B.bc, B.ctrl, B.part, npart, B.cap);
+        if (ce == hipSuccess) ce = hj::launch_batch_advance(B.bc, B.cap);
+    }
+    const hipError_t ee = hipStreamEndCapture(B.cap, &graph);
+    if (ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(ce, "capturing the batch cycle");
+    }
+    HJ_HIP(ee);
+    {
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(ie, "hipGraphInstantiate");
+        }
+    }
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    };
+
+    // replay with one replay of lookahead; poll the control blocks in between
+    const int64_t replays = (p->max_cycles + 1 + K - 1) / K;  // cycles 0 .. max_cycles
+    int64_t launched = 0;
+    auto enqueue = [&](int slot) -> hipError_t {
+        hipError_t e = hipGraphLaunch(exec, st);
+        if (e == hipSuccess) ++launched;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(B.host + (size_t)slot * nprob, B.ctrl, (size_t)nprob * sizeof(hj::Ctrl),
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(S.ev[slot], st);
+        return e;
+    };
+    hipError_t le = enqueue(0);
+    int slot = 0;
+    while (le == hipSuccess) {
+        const bool more = launched < replays;
+        if (more && (le = enqueue(slot ^ 1)) != hipSuccess) break;
+        if ((le = hipEventSynchronize(S.ev[slot])) != hipSuccess) break;
+        bool running = false;
+        for (int64_t i = 0; i < nprob && !running; ++i)
+            running = B.host[(size_t)slot * nprob + i].status == hj::ST_RUNNING;
+        if (!running || !more) break;
+        slot ^= 1;
+    }
+    if (le == hipSuccess) le = hj::launch_batch_finalize(idt, B.probs, (int)nprob, B.ctrl, st);
+    if (le == hipSuccess)
+        le = hipMemcpyAsync(B.host, B.ctrl, (size_t)nprob * sizeof(hj::Ctrl), hipMemcpyDeviceToHost, st);
+    if (le == hipSuccess) le = hipStreamSynchronize(st);
+    cleanup();
+    if (le != hipSuccess) return hip_fail(le, "batch replay");
+
+    hj_status status = HJ_OK;
+    int64_t bad = -1;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const hj::Ctrl &c = B.host[i];
+        const int s_dim = probs[i].dim == 2 ? P2.s : P1.s;
+        if (infos) {
+            infos[i].cycles = c.done_cycle;
+            infos[i].sweeps = c.done_cycle * s_dim;
+            infos[i].r0_norm = std::sqrt(c.r0sq);
+            infos[i].rel_residual = c.r0sq > 0.0 ? std::sqrt(c.last_rsq) / std::sqrt(c.r0sq) : 0.0;
+            if (!std::isfinite(c.last_rsq)) infos[i].rel_residual = NAN;
+        }
+        if (c.status == hj::ST_NONFINITE) {
+            status = HJ_ERR_NONFINITE;
+            bad = i;
+        } else if (c.status != hj::ST_CONVERGED && tol > 0.0 && status == HJ_OK) {
+            status = HJ_ERR_NOT_CONVERGED;
+            bad = i;
+        }
+    }
+    if (status == HJ_ERR_NONFINITE)
+        return fail(status, "problem " + std::to_string(bad) + ": residual norm became non-finite");
+    if (status == HJ_ERR_NOT_CONVERGED)
+        return fail(status, "problem " + std::to_string(bad) + " reached max_cycles before rel_tol");
+    return HJ_OK;
 }
 
 hj_status hj_solve_vc_2d(const hj_vc_problem *prob, const double *f, double *u, const hj_params *p,

@@ -16,11 +16,11 @@ struct Ctrl {
     double last_rsq;     // ||r_c||^2 of the latest judged iterate
     int64_t iter;        // one past the latest judged iterate
     int64_t done_cycle;  // first c that met the tolerance (or went non-finite); -1 otherwise
-    int32_t status;      // 0 running, 1 converged, 2 non-finite
+    int32_t status;      // 0 running, 1 converged, 2 non-finite, 3 stopped at max_cycles
     int32_t pad;
 };
 
-enum : int32_t { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NONFINITE = 2 };
+enum : int32_t { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NONFINITE = 2, ST_LIMIT = 3 };
 
 // ---------------------------------------------------------------------------
 // Tile partition along one axis (subdomains of Sec. 3.3, overlap of Sec. 3.5).

@@ -89,6 +89,51 @@ hipError_t launch_grad_a_vc(const GeomVC &g, const double *u, const double *lam,
                             int64_t bstride, double *grad, int64_t ldg, hipStream_t st);
 
 // mixed precision helpers (hj_refine.hip)
+// ---------------------------------------------------------------- batches
+// One problem of a batch on the device.  Buffer 0 is the caller's x, buffer 1
+// a scratch array of the same layout; iterate c lives in buffer c & 1.
+struct BProb {
+    int32_t dim;     // 1 or 2
+    int32_t pad;
+    Geom2 g2;        // dim 2
+    Geom1 g1;        // dim 1
+    const void *f;
+    void *x;
+    void *s1;
+    int64_t item0;   // first work item of this problem in its dimension's list
+    int64_t nitems;  // work items: 2D tiles, or 1D tile groups
+    int64_t part0;   // first residual partial slot
+};
+
+struct BCtl {
+    int64_t cycle;       // cycle the next kernels run (advanced on the device)
+    int64_t max_cycles;  // problems still running after iterate max_cycles stop
+    double tol;          // relative tolerance (<= 0: run max_cycles cycles)
+};
+
+struct BatchLaunch {
+    const BProb *probs;
+    const int32_t *owner;  // problem of each work item
+    int64_t nitems;
+    const BCtl *bc;
+    const Ctrl *ctrl;      // one per problem
+    double *part;          // 2 x npart partial slots (by cycle parity)
+    int64_t npart;
+    int s;
+};
+
+bool batch2d_supported(int tx, int ty);
+// iso: the work list holds only problems with hx == hy (else only the others)
+hipError_t launch_batch_cycle2d(int dt, int tx, int ty, bool iso, const BatchLaunch &L, hipStream_t st);
+hipError_t launch_batch_cycle1d(int dt, int t, const BatchLaunch &L, hipStream_t st);
+hipError_t launch_batch_judge(const BProb *probs, int nprob, const BCtl *bc, Ctrl *ctrl,
+                              const double *part, int64_t npart, hipStream_t st);
+hipError_t launch_batch_advance(BCtl *bc, hipStream_t st);
+hipError_t launch_batch_init(Ctrl *ctrl, int nprob, BCtl *bc, int64_t max_cycles, double tol,
+                             hipStream_t st);
+hipError_t launch_batch_finalize(int dt, const BProb *probs, int nprob, const Ctrl *ctrl,
+                                 hipStream_t st);
+
 int64_t resid2d_mixed_blocks(const Geom2 &g);
 hipError_t launch_resid2d_f64_to_f32(const Geom2 &g, const double *f, const double *x, float *r32,
                                      double *part, hipStream_t st);

@@ -1,0 +1,349 @@
+// hj_tiles.h -- the per-tile bodies of the hierarchical cycle (Sec. 3.3,
+// Sec. 4.1), shared by the one-problem kernels and the batched persistent
+// kernels: the update and residual formulas, the register-resident 2D tile
+// and the 1D LDS tile group.  Device code only; include after hj_launch.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "hj_launch.h"
+
+namespace hj {
+namespace {
+
+// ---------------------------------------------------------------- updates
+// 2D: iso  -> (h^2 f + ((W + E) + (S + N))) * 0.25      (Sec. 4.2, dx == dy)
+//     else -> (f + (wx (W + E) + wy (S + N))) * dinv    (Sec. 4.2 general form)
+template <typename T, bool ISO>
+__device__ __forceinline__ T upd2(T b, T w, T e, T s, T n, T wx, T wy, T dinv)
+{
+    if (ISO) return (b + ((w + e) + (s + n))) * T(0.25);
+    return (b + (wx * (w + e) + wy * (s + n))) * dinv;
+}
+
+// 1D: (h^2 f + (W + E)) * 0.5                            (Sec. 3.4)
+template <typename T>
+__device__ __forceinline__ T upd1(T bh, T w, T e)
+{
+    return (bh + (w + e)) * T(0.5);
+}
+
+// r = f - A x in FP64
+__device__ __forceinline__ double res2(double f, double x, double w, double e, double s, double n,
+                                       double wx, double wy)
+{
+    return f - (wx * ((2.0 * x - w) - e) + wy * ((2.0 * x - s) - n));
+}
+
+__device__ __forceinline__ double res1(double f, double x, double w, double e, double w1)
+{
+    return f - w1 * ((2.0 * x - w) - e);
+}
+
+constexpr int kNT = 256;  // threads per workgroup of every kernel here
+
+// ============================================================================
+// 2D hierarchical cycle, register-resident.  A workgroup of W wavefronts takes
+// one full tile of TX = 16*C columns by TY = 4*R*W rows.  Thread t belongs to
+// row group k = t / 16 (4 per wavefront, NG = 4W in all) and lane j = t % 16
+// of that group, and holds rows [kR, kR + R) x columns [jC, jC + C) of the
+// tile in VGPRs, so a 16-lane DPP row spans the whole tile width.
+// x-neighbours in other lanes come from DPP row shifts; y-neighbours in other
+// row groups through LDS interface rows, double-buffered so that one barrier
+// per sweep suffices.  The frozen halo sits in registers (columns -1 and TX,
+// in the first / last lane of each DPP row) and in LDS (rows -1 and TY).
+// Used when the grid holds at least one full tile in each direction.
+//
+// Isotropic update in FMA form: fma(S, 1/4, h^2 f / 4) with S = (W + E) +
+// (S + N) equals (h^2 f + S) * 1/4 rounded the two-step way, because scaling
+// by a power of two commutes with rounding; this holds whenever the values
+// involved are normal numbers (magnitudes above 2^-1020 in FP64, 2^-124 in
+// FP32).
+// ============================================================================
+constexpr int kDppRowShr1 = 0x111;  // lane i <- lane i - 1 of its 16-lane row
+constexpr int kDppRowShl1 = 0x101;  // lane i <- lane i + 1 of its 16-lane row
+
+// Lanes whose source falls outside the 16-lane row receive 0 (bound_ctrl).
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+
+// s * 1/4 + b with one rounding, in the three-address VOP3 form (the compiler's
+// two-address v_fmac would first copy b, which stays live across sweeps)
+// (0.25 is not an inline constant and VOP3 takes no literal: it rides in SGPRs)
+__device__ __forceinline__ double fma_quarter(double sv, double b)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(sv), "s"(0.25), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ float fma_quarter(float sv, float b)
+{
+    float r;
+    asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(sv), "s"(0.25f), "v"(b));
+    return r;
+}
+
+// One cycle of tile `tile` (row-major tile index over g's partition) by a
+// workgroup of 64 W threads.  Returns this thread's share of ||r||^2 of xin
+// over the owned points (RES), else 0.  A caller that runs several tiles in a
+// row must place a barrier between them (LDS is reused).
+template <typename T, int C, int R, int W, bool RES, bool ISO>
+__device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T *__restrict__ f,
+                                              const T *__restrict__ xin, T *__restrict__ xout,
+                                              int nsub)
+{
+    constexpr int TX = 16 * C, TY = 4 * R * W, NG = 4 * W;
+    __shared__ T s_top[2][NG][TX];  // first row of each row group, by sweep parity
+    __shared__ T s_bot[2][NG][TX];  // last row of each row group
+    __shared__ T s_halo[2][TX];     // frozen rows -1 and TY
+
+    const int k = (int)threadIdx.x >> 4, j = (int)threadIdx.x & 15;
+    const int bi = tile / g.ntx, bj = tile - bi * g.ntx;
+    const int r0 = axis_origin(g.ny, TY, g.oy, bi);
+    const int c0 = axis_origin(g.nx, TX, g.ox, bj);
+    const int64_t ld = g.ld;
+    const int lr0 = k * R, lc0 = j * C;
+    const int64_t base = (int64_t)(r0 + lr0) * ld + c0 + lc0;
+
+    // step 1: tile, halo and f into registers / LDS
+    T x[R][C], bq[R][C], hw[R], he[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            x[i][c] = xin[base + (int64_t)i * ld + c];
+            bq[i][c] = f[base + (int64_t)i * ld + c];  // f for now, scaled after the residual
+        }
+        hw[i] = (j == 0 && c0 > 0) ? xin[base + (int64_t)i * ld - 1] : T(0);
+        he[i] = (j == 15 && c0 + TX < g.nx) ? xin[base + (int64_t)i * ld + C] : T(0);
+    }
+    if (k == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            s_halo[0][lc0 + c] = r0 > 0 ? xin[(int64_t)(r0 - 1) * ld + c0 + lc0 + c] : T(0);
+    }
+    if (k == NG - 1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            s_halo[1][lc0 + c] =
+                r0 + TY < g.ny ? xin[(int64_t)(r0 + TY) * ld + c0 + lc0 + c] : T(0);
+    }
+    const int rlo = axis_own_begin(g.ny, TY, g.oy, bi) - r0 - lr0;
+    const int rhi = axis_own_end(g.ny, TY, g.oy, bi, g.nty) - r0 - lr0;
+    const int clo = axis_own_begin(g.nx, TX, g.ox, bj) - c0 - lc0;
+    const int chi = axis_own_end(g.nx, TX, g.ox, bj, g.ntx) - c0 - lc0;
+
+    const T wx = T(g.wx), wy = T(g.wy), dinv = T(g.dinv);
+    T up[C], dn[C];
+    // Publish this group's first / last rows for the sweep of parity par and
+    // fetch the neighbouring groups' (or the frozen halo rows).  A buffer is
+    // rewritten two sweeps later, after a barrier that every thread reaches
+    // only once its reads from it are done.
+    auto exchange = [&](int par) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            s_top[par][k][lc0 + c] = x[0][c];
+            s_bot[par][k][lc0 + c] = x[R - 1][c];
+        }
+        __syncthreads();
+        const T *pu = k == 0 ? &s_halo[0][lc0] : &s_bot[par][k - 1][lc0];
+        const T *pd = k == NG - 1 ? &s_halo[1][lc0] : &s_top[par][k + 1][lc0];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            up[c] = pu[c];
+            dn[c] = pd[c];
+        }
+    };
+
+    // One sub-iteration over the lane's rows, top to bottom, in place: prev
+    // keeps the old row above.  FIRST: bq still holds f; it also accumulates
+    // the residual of the incoming iterate over the owned points and scales f
+    // (h^2 f / 4 when isotropic) as it goes.
+    double rsq = 0.0;
+    const T hh = T(g.hh);
+    auto sweep = [&](auto first_tag) {
+        constexpr bool FIRST = decltype(first_tag)::value;
+        T prev[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) prev[c] = up[c];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const T wl = dpp_shift<kDppRowShr1>(x[i][C - 1]);
+            const T er = dpp_shift<kDppRowShl1>(x[i][0]);
+            T nw[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T w = c > 0 ? x[i][c - 1] : wl;
+                const T e = c < C - 1 ? x[i][c + 1] : er;
+                T we = w + e;
+                // the halo registers are 0 except in the first / last lane of a
+                // DPP row, where the shifted value is 0: the sum stays W + E
+                if (c == 0) we = we + hw[i];
+                if (c == C - 1) we = we + he[i];
+                const T below = i < R - 1 ? x[i + 1][c] : dn[c];
+                const T sn = prev[c] + below;
+                if (FIRST) {
+                    if (RES && i >= rlo && i < rhi && c >= clo && c < chi) {
+                        const double wa = c > 0 ? (double)w : (double)wl + (double)hw[i];
+                        const double ea = c < C - 1 ? (double)e : (double)er + (double)he[i];
+                        const double rr = res2((double)bq[i][c], (double)x[i][c], wa, ea,
+                                               (double)prev[c], (double)below, g.wx, g.wy);
+                        rsq += rr * rr;
+                    }
+                    if (ISO) bq[i][c] = (hh * bq[i][c]) * T(0.25);
+                }
+                if (ISO) nw[c] = fma_quarter(we + sn, bq[i][c]);
+                else nw[c] = (bq[i][c] + (wx * we + wy * sn)) * dinv;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                prev[c] = x[i][c];
+                x[i][c] = nw[c];
+            }
+        }
+    };
+
+    // step 2: nsub sub-iterations with the halo frozen
+    exchange(0);
+    sweep(std::true_type{});
+    for (int it = 1; it < nsub; ++it) {
+        exchange(it & 1);
+        sweep(std::false_type{});
+    }
+
+    // step 3: owned points back to global memory
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (i >= rlo && i < rhi && c >= clo && c < chi) xout[base + (int64_t)i * ld + c] = x[i][c];
+
+    return rsq;
+}
+
+
+// ============================================================================
+// 1D hierarchical cycle.  Tiles of TT points; a workgroup holds G = kNT / TT
+// tiles (TT <= kNT) or one tile with TT / kNT points per thread.
+// ============================================================================
+// One cycle of the tile group `blk` (tiles blk*G .. blk*G + G - 1) by a
+// workgroup of kNT threads.  Returns this thread's share of ||r||^2 of xin
+// over the owned points (RES), else 0.  Several groups in a row need a
+// barrier between them (LDS is reused).
+template <typename T, int TT, bool RES>
+__device__ __forceinline__ double lds_tiles_1d(const Geom1 &g, int64_t blk, const T *__restrict__ f,
+                                               const T *__restrict__ xin, T *__restrict__ xout, int s)
+{
+    constexpr int G = TT <= kNT ? kNT / TT : 1;
+    constexpr int PER = TT <= kNT ? 1 : TT / kNT;
+    constexpr int P = TT + 2;
+    __shared__ T buf[2][G * P];
+
+    const int64_t n = g.n;
+    const int ni = n < TT ? (int)n : TT;  // points per tile
+    const int ntile = (int)g.nt;
+    const int nint = n > 0x7fffffff ? 0x7fffffff : (int)n;
+
+    for (int i = threadIdx.x; i < G * P; i += kNT) {
+        const int gi = i / P, lc = i - gi * P;
+        const int64_t tile = blk * G + gi;
+        T v = T(0);
+        if (tile < ntile) {
+            const int64_t gp = (int64_t)axis_origin(nint, TT, g.o, (int)tile) + lc - 1;
+            if (gp >= 0 && gp < n) v = xin[gp];
+        }
+        buf[0][i] = v;
+        buf[1][i] = v;
+    }
+
+    const int gi = TT <= kNT ? (int)threadIdx.x / TT : 0;
+    const int64_t tile = blk * G + gi;
+    const bool live = tile < ntile;
+    const int64_t x0 = live ? axis_origin(nint, TT, g.o, (int)tile) : 0;
+    const int lo = live ? axis_own_begin(nint, TT, g.o, (int)tile) - (int)x0 : 0;
+    const int hi = live ? axis_own_end(nint, TT, g.o, (int)tile, ntile) - (int)x0 : 0;
+    const T hh = T(g.hh);
+    T fb[PER], val[PER];
+    double fr[RES ? PER : 1];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int lc = TT <= kNT ? (int)threadIdx.x % TT : (int)threadIdx.x + j * kNT;
+        T fv = T(0);
+        if (live && lc < ni) fv = f[x0 + lc];
+        fb[j] = hh * fv;
+        if (RES) fr[RES ? j : 0] = (double)fv;
+        val[j] = T(0);
+    }
+    __syncthreads();
+
+    double rsq = 0.0;
+    if (RES) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int lc = TT <= kNT ? (int)threadIdx.x % TT : (int)threadIdx.x + j * kNT;
+            if (live && lc >= lo && lc < hi) {
+                const int a = gi * P + lc + 1;
+                const double rr = res1(fr[RES ? j : 0], (double)buf[0][a], (double)buf[0][a - 1],
+                                       (double)buf[0][a + 1], g.w1);
+                rsq += rr * rr;
+            }
+        }
+    }
+
+    for (int k = 0; k < s; ++k) {
+        const T *cur = buf[k & 1];
+        T *nxt = buf[(k & 1) ^ 1];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int lc = TT <= kNT ? (int)threadIdx.x % TT : (int)threadIdx.x + j * kNT;
+            if (live && lc < ni) {
+                const int a = gi * P + lc + 1;
+                const T v = upd1<T>(fb[j], cur[a - 1], cur[a + 1]);
+                nxt[a] = v;
+                val[j] = v;
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int lc = TT <= kNT ? (int)threadIdx.x % TT : (int)threadIdx.x + j * kNT;
+        if (live && lc >= lo && lc < hi) xout[x0 + lc] = val[j];
+    }
+
+    return rsq;
+}
+
+
+// Register-resident shape for a TX x TY tile: C columns and R rows per lane,
+// W wavefronts.  Up to 32 x 32 one wavefront holds the tile (R = TY / 4);
+// taller tiles use 4 rows per lane (8 at TX = 32) and more wavefronts, which
+// keeps the per-lane footprint small enough for three or more waves per SIMD.
+template <int TX, int TY>
+struct RegShape {
+    static constexpr int C = TX / 16;
+    static constexpr int R = (TX <= 64 && TY <= 32) ? TY / 4 : (TX == 32 ? 8 : 4);
+    static constexpr int W = TY / (4 * R);
+    static constexpr bool ok = (TX == 32 || TX == 64 || TX == 128) && TY >= 16 && TY <= 128 &&
+                               W >= 1 && 4 * R * W == TY;
+};
+
+}  // namespace
+}  // namespace hj

@@ -70,6 +70,21 @@ class AdjointDesc(ctypes.Structure):
                 ("params", Params)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("flags", ctypes.c_int32), ("nx", ctypes.c_int64),
+                ("ny", ctypes.c_int64), ("ld", ctypes.c_int64), ("hx", ctypes.c_double),
+                ("hy", ctypes.c_double), ("f", ctypes.c_void_p), ("x", ctypes.c_void_p)]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [("p2", Params), ("p1", Params), ("rel_tol", ctypes.c_double),
+                ("max_cycles", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("graph_cycles", ctypes.c_int32), ("flags", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+HJ_BATCH_AUTOTUNE = 0x1
+
+
 class _Info(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int64), ("sweeps", ctypes.c_int64),
                 ("rel_residual", ctypes.c_double), ("r0_norm", ctypes.c_double)]
@@ -96,7 +111,8 @@ class HJError(RuntimeError):
 
 _lib = None
 EXPORTS = ("hj_params_default", "hj_solve_1d", "hj_solve_2d", "hj_solve_2d_refined", "hj_residual",
-           "hj_solve_batched", "hj_solve_vc_2d", "hj_vc_grad_a", "hj_solve_adjoint", "hj_axis_tiles",
+           "hj_solve_batched", "hj_autotune", "hj_solve_vc_2d", "hj_vc_grad_a", "hj_solve_adjoint",
+           "hj_axis_tiles",
            "hj_status_string", "hj_last_error", "hj_version")
 
 
@@ -121,8 +137,10 @@ def load():
     lib.hj_solve_2d_refined.restype = i32
     lib.hj_residual.argtypes = [i32, i64, i64, i64, f64, f64, i32, vp, vp, vp, ctypes.POINTER(f64), vp]
     lib.hj_residual.restype = i32
-    lib.hj_solve_batched.argtypes = [vp, i64, P, vp, vp]
+    lib.hj_solve_batched.argtypes = [ctypes.POINTER(Problem), i64, ctypes.POINTER(BatchParams), vp, I]
     lib.hj_solve_batched.restype = i32
+    lib.hj_autotune.argtypes = [i32, i64, i64, i32, vp, P, ctypes.POINTER(f64)]
+    lib.hj_autotune.restype = i32
     lib.hj_solve_vc_2d.argtypes = [ctypes.POINTER(VCProblem), vp, vp, P, vp, I]
     lib.hj_solve_vc_2d.restype = i32
     lib.hj_vc_grad_a.argtypes = [ctypes.POINTER(VCProblem), vp, vp, vp, i64, vp]
@@ -272,6 +290,81 @@ def solve_2d_refined(f, x, h=None, *, hx=None, hy=None, tile=(64, 32), s=8, over
     if st == HJ_OK or (st == HJ_ERR_NOT_CONVERGED and allow_not_converged):
         return out
     raise HJError(st, last_error())
+
+
+def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 18), tile_1d=256,
+                  s_1d=16, overlap_1d=30, max_cycles=1_000_000, graph_cycles=8, autotune=False,
+                  allow_not_converged=False) -> list:
+    """Solve many independent problems together (hj_solve_batched).
+
+    problems: sequence of (f, x, h) or (f, x, hx, hy); f, x GPU tensors of one
+    dtype, shape (n,) for 1D and (ny, nx) for 2D (row-major).  Each x is updated
+    in place.  2D problems use the cycle (tile, s, overlap), 1D problems
+    (tile_1d, s_1d, overlap_1d); autotune=True lets the library choose both.
+    Returns one Info per problem."""
+    import torch
+    if not problems:
+        return []
+    arr = (Problem * len(problems))()
+    dt = None
+    for i, pr in enumerate(problems):
+        f, x = pr[0], pr[1]
+        hx = float(pr[2])
+        hy = float(pr[3]) if len(pr) > 3 else hx
+        _check_pair(f, x)
+        code = _dtype_code(f)
+        if dt is None:
+            dt = code
+        elif code != dt:
+            raise ValueError("all problems of a batch share one dtype")
+        q = arr[i]
+        q.flags = 0
+        q.hx, q.hy = hx, hy
+        q.f, q.x = f.data_ptr(), x.data_ptr()
+        if f.dim() == 1:
+            if not (f.is_contiguous() and x.is_contiguous()):
+                raise ValueError("1D tensors must be contiguous")
+            q.dim, q.nx, q.ny, q.ld = 1, f.numel(), 1, f.numel()
+        elif f.dim() == 2:
+            ld = _ld(f)
+            if _ld(x) != ld:
+                raise ValueError("f and x must share the row stride")
+            q.dim, q.ny, q.nx, q.ld = 2, f.shape[0], f.shape[1], ld
+        else:
+            raise ValueError("problems are 1D or 2D tensors")
+    bp = BatchParams()
+    bp.p2 = make_params(tile, s, "hierarchical", rel_tol, max_cycles, 0, overlap)
+    bp.p1 = make_params(tile_1d, s_1d, "hierarchical", rel_tol, max_cycles, 0, overlap_1d)
+    bp.rel_tol = rel_tol
+    bp.max_cycles = max_cycles
+    bp.dtype = dt
+    bp.graph_cycles = graph_cycles
+    bp.flags = HJ_BATCH_AUTOTUNE if autotune else 0
+    infos = (_Info * len(problems))()
+    f0 = problems[0][0]
+    with _device(f0):
+        st = load().hj_solve_batched(arr, len(problems), ctypes.byref(bp), _stream(f0), infos)
+    if st != HJ_OK and not (st == HJ_ERR_NOT_CONVERGED and allow_not_converged):
+        raise HJError(st, last_error())
+    return [Info(st, i.cycles, i.sweeps, i.rel_residual, i.r0_norm) for i in infos]
+
+
+def autotune(dim, nx, ny=1, dtype=None):
+    """Fastest cycle shape per sweep for an nx x ny (1D: nx) grid (hj_autotune).
+    Returns (tile, s, overlap, microseconds per sweep); tile and overlap are
+    (x, y) pairs in 2D and ints in 1D."""
+    import torch
+    dtype = torch.float64 if dtype is None else dtype
+    code = HJ_F64 if dtype == torch.float64 else HJ_F32
+    p = Params()
+    us = ctypes.c_double()
+    st = load().hj_autotune(dim, nx, ny, code, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                            ctypes.byref(p), ctypes.byref(us))
+    if st != HJ_OK:
+        raise HJError(st, last_error())
+    if dim == 2:
+        return (p.tile_x, p.tile_y), p.s, (p.overlap_x, p.overlap_y), us.value
+    return p.tile_x, p.s, p.overlap_x, us.value
 
 
 def _vc_problem(a, f, hx, hy):

@@ -120,10 +120,74 @@ def test_refined_solve_rejects_invalid_arguments():
     assert call(rp(), h=-1.0) == hj.HJ_ERR_INVALID_ARG
 
 
-def test_future_entry_points_report_unsupported():
+def _batch(n2=1, n1=1, **kw):
+    arr = (hj.Problem * (n2 + n1))()
+    for i in range(n2 + n1):
+        q = arr[i]
+        q.dim, q.flags = (2, 0) if i < n2 else (1, 0)
+        q.nx, q.ny, q.ld = (300, 200, 300) if i < n2 else (5000, 1, 5000)
+        q.hx = q.hy = 0.01
+        q.f, q.x = FAKE, FAKE + 0x1000
+    bp = hj.BatchParams()
+    bp.p2 = _params(tile_x=64, tile_y=64, s=10, overlap_x=18, overlap_y=18)
+    bp.p1 = _params(tile_x=256, s=16, overlap_x=30)
+    bp.rel_tol, bp.max_cycles, bp.dtype, bp.graph_cycles, bp.flags = 1e-8, 100, 0, 8, 0
+    for k, v in kw.items():
+        if k.startswith("q_"):
+            setattr(arr[0], k[2:], v)
+        else:
+            setattr(bp, k, v)
+    return arr, bp
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({"q_dim": 3}, hj.HJ_ERR_INVALID_ARG),
+    ({"q_flags": 1}, hj.HJ_ERR_INVALID_ARG),
+    ({"q_ld": 100}, hj.HJ_ERR_INVALID_ARG),             # ld < nx
+    ({"q_hy": 0.0}, hj.HJ_ERR_INVALID_ARG),
+    ({"q_hx": float("inf")}, hj.HJ_ERR_INVALID_ARG),
+    ({"q_x": None}, hj.HJ_ERR_INVALID_ARG),
+    ({"q_f": FAKE + 3}, hj.HJ_ERR_INVALID_ARG),         # misaligned
+    ({"q_nx": 0}, hj.HJ_ERR_INVALID_ARG),
+    ({"dtype": 7}, hj.HJ_ERR_INVALID_ARG),
+    ({"max_cycles": 0}, hj.HJ_ERR_INVALID_ARG),
+    ({"graph_cycles": 2000}, hj.HJ_ERR_INVALID_ARG),
+    ({"flags": 4}, hj.HJ_ERR_INVALID_ARG),
+    ({"rel_tol": float("nan")}, hj.HJ_ERR_INVALID_ARG),
+    ({"q_nx": 40, "q_ld": 40}, hj.HJ_ERR_UNSUPPORTED),   # 2D problem smaller than the tile
+])
+def test_batched_rejects_invalid_arguments(kw, code):
     lib = hj.load()
-    p = _params()
-    assert lib.hj_solve_batched(None, 0, ctypes.byref(p), None, None) == hj.HJ_ERR_UNSUPPORTED
+    arr, bp = _batch(**kw)
+    infos = (hj._Info * len(arr))()
+    assert lib.hj_solve_batched(arr, len(arr), ctypes.byref(bp), None, infos) == code, hj.last_error()
+    assert hj.last_error()
+
+
+def test_batched_rejects_unsupported_shapes_and_empty_tables():
+    lib = hj.load()
+    arr, bp = _batch()
+    assert lib.hj_solve_batched(None, 1, ctypes.byref(bp), None, None) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_solve_batched(arr, 0, ctypes.byref(bp), None, None) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_solve_batched(arr, 2, None, None, None) == hj.HJ_ERR_INVALID_ARG
+    for p2 in (_params(tile_x=128, tile_y=64), _params(tile_x=16, tile_y=16),
+               _params(tile_x=64, tile_y=64, method=hj.HJ_GLOBAL)):
+        arr, bp = _batch()
+        bp.p2 = p2
+        assert lib.hj_solve_batched(arr, 2, ctypes.byref(bp), None, None) == hj.HJ_ERR_UNSUPPORTED
+    arr, bp = _batch()
+    bp.p1 = _params(tile_x=48)
+    assert lib.hj_solve_batched(arr, 2, ctypes.byref(bp), None, None) == hj.HJ_ERR_UNSUPPORTED
+
+
+def test_autotune_validates():
+    lib = hj.load()
+    p = hj.Params()
+    us = ctypes.c_double()
+    assert lib.hj_autotune(3, 64, 64, 0, None, ctypes.byref(p), ctypes.byref(us)) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_autotune(2, 0, 64, 0, None, ctypes.byref(p), ctypes.byref(us)) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_autotune(2, 64, 64, 5, None, ctypes.byref(p), ctypes.byref(us)) == hj.HJ_ERR_INVALID_ARG
+    assert lib.hj_autotune(1, 64, 1, 0, None, None, None) == hj.HJ_ERR_INVALID_ARG
 
 
 def test_variable_coefficient_entry_points_validate():

@@ -1,0 +1,158 @@
+"""GPU parity of the batched solve (hj_solve_batched): many 2D and 1D problems
+of uneven sizes, one launch per cycle over all of them, cycles replayed from a
+captured HIP graph.  Every problem must end exactly where its own oracle solve
+with the same cycle shape ends (bit for bit in FP64, same cycle count), for
+any number of cycles per graph replay, and whatever ran on the stream between
+replays."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2006_16465_amd import hj
+from paper_2006_16465_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+T2, S2, O2 = (64, 64), 10, (18, 18)
+T1, S1, O1 = 256, 16, 30
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.double().cpu().numpy()
+
+
+def make_batch(seed=0):
+    """Square and rectangular 2D grids (one with hx != hy) and 1D grids."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for ny, nx in ((64, 64), (70, 97), (128, 150), (200, 133), (96, 64)):
+        f = W.rhs_2d_modes(nx, ny, 8, 0.0, int(rng.integers(1 << 30)))
+        probs.append(("2d", f, 1.0 / (nx + 1), 1.0 / (ny + 1)))
+    f = W.rhs_2d_modes(90, 80, 8, 0.0, 3)
+    probs.append(("2d", f, 1.0 / 91, 1.0 / 91))  # hx == hy on a rectangle
+    for n in (1000, 1537, 4000):
+        probs.append(("1d", W.rhs_1d_modes(n, 8, int(rng.integers(1 << 30))), 1.0 / (n + 1), None))
+    return probs
+
+
+def oracle_solve(orc, pr, tol, max_cycles=1_000_000):
+    kind, f, hx, hy = pr
+    if kind == "2d":
+        return orc.solve_2d(f, np.zeros_like(f), hx, hy, tile=T2, s=S2, overlap=O2, tol=tol,
+                            max_cycles=max_cycles)
+    return orc.solve_1d(f, np.zeros_like(f), hx, tile=T1, s=S1, tol=tol, max_cycles=max_cycles,
+                        overlap=O1)
+
+
+def gpu_batch(probs, dtype=torch.float64, **kw):
+    xs = [torch.zeros_like(dev(f, dtype)) for _, f, _, _ in probs]
+    fs = [dev(f, dtype) for _, f, _, _ in probs]
+    table = [(F, X, hx, hy if hy else hx) for (_, _, hx, hy), F, X in zip(probs, fs, xs)]
+    infos = hj.solve_batched(table, tile=T2, s=S2, overlap=O2, tile_1d=T1, s_1d=S1, overlap_1d=O1, **kw)
+    return [host(X) for X in xs], infos
+
+
+@pytest.mark.parametrize("graph_cycles", [8, 3, 1])
+def test_batch_matches_oracle_per_problem(orc, graph_cycles):
+    probs = make_batch(0)
+    got, infos = gpu_batch(probs, rel_tol=1e-8, graph_cycles=graph_cycles)
+    for i, pr in enumerate(probs):
+        xo, co, relo, r0o = oracle_solve(orc, pr, 1e-8)
+        say(f"batch[{i}] {pr[0]} {pr[1].shape}: gpu cycles {infos[i].cycles} oracle {co}")
+        assert infos[i].status == hj.HJ_OK
+        assert infos[i].cycles == co
+        assert np.array_equal(got[i], xo)
+        assert abs(infos[i].rel_residual - relo) <= 1e-9 * relo
+        assert abs(infos[i].r0_norm - r0o) <= 1e-12 * r0o
+
+
+def test_batch_fixed_cycles_and_repeated_calls(orc):
+    probs = make_batch(1)
+    first, _ = gpu_batch(probs, rel_tol=0.0, max_cycles=7, graph_cycles=3)
+    # eager work on the stream between the two calls (a new graph each call)
+    junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+    junk.mul_(2.0).sum()
+    second, infos = gpu_batch(probs, rel_tol=0.0, max_cycles=7, graph_cycles=5)
+    for i, (kind, f, hx, hy) in enumerate(probs):
+        if kind == "2d":
+            want = orc.hier_2d(f, np.zeros_like(f), hx, hy, T2, S2, 7, O2)
+        else:
+            want = orc.hier_1d(f, np.zeros_like(f), hx, T1, S1, 7, O1)
+        assert infos[i].status == hj.HJ_OK and infos[i].cycles == 7
+        assert np.array_equal(first[i], want), f"problem {i}, first call"
+        assert np.array_equal(second[i], want), f"problem {i}, second call"
+
+
+def test_batch_not_converged_keeps_last_iterate(orc):
+    probs = make_batch(2)
+    got, infos = gpu_batch(probs, rel_tol=1e-12, max_cycles=4, allow_not_converged=True)
+    assert any(i.status == hj.HJ_ERR_NOT_CONVERGED for i in infos)
+    for i, (kind, f, hx, hy) in enumerate(probs):
+        c = infos[i].cycles
+        assert 0 <= c <= 4
+        if kind == "2d":
+            want = orc.hier_2d(f, np.zeros_like(f), hx, hy, T2, S2, c, O2)
+        else:
+            want = orc.hier_1d(f, np.zeros_like(f), hx, T1, S1, c, O1)
+        assert np.array_equal(got[i], want)
+    with pytest.raises(hj.HJError):
+        gpu_batch(probs, rel_tol=1e-12, max_cycles=4)
+
+
+def test_batch_fp32_within_1e5_of_fp64_oracle(orc):
+    probs = make_batch(3)
+    got, _ = gpu_batch(probs, dtype=torch.float32, rel_tol=0.0, max_cycles=12)
+    for i, (kind, f, hx, hy) in enumerate(probs):
+        if kind == "2d":
+            want = orc.hier_2d(f, np.zeros_like(f), hx, hy, T2, S2, 12, O2)
+        else:
+            want = orc.hier_1d(f, np.zeros_like(f), hx, T1, S1, 12, O1)
+        assert np.linalg.norm(got[i] - want) <= 1e-5 * np.linalg.norm(want)
+
+
+def test_batch_equals_single_problem_solves():
+    probs = make_batch(4)
+    got, infos = gpu_batch(probs, rel_tol=1e-7)
+    for i, (kind, f, hx, hy) in enumerate(probs):
+        X = torch.zeros_like(dev(f))
+        if kind == "2d":
+            one = hj.solve_2d(dev(f), X, hx=hx, hy=hy, tile=T2, s=S2, overlap=O2, rel_tol=1e-7)
+        else:
+            one = hj.solve_1d(dev(f), X, hx, tile=T1, s=S1, overlap=O1, rel_tol=1e-7)
+        assert one.cycles == infos[i].cycles
+        assert np.array_equal(host(X), got[i])
+
+
+def residual_np(kind, f, x, hx, hy):
+    if kind == "1d":
+        xp = np.pad(x, 1)
+        return np.linalg.norm(f - (2 * x - xp[:-2] - xp[2:]) / hx ** 2) / np.linalg.norm(f)
+    xp = np.pad(x, 1)
+    ax = (2 * x - xp[1:-1, :-2] - xp[1:-1, 2:]) / hx ** 2 + (2 * x - xp[:-2, 1:-1] - xp[2:, 1:-1]) / hy ** 2
+    return np.linalg.norm(f - ax) / np.linalg.norm(f)
+
+
+def test_autotuned_batch_converges():
+    probs = make_batch(5)
+    xs = [torch.zeros_like(dev(f)) for _, f, _, _ in probs]
+    table = [(dev(f), X, hx, hy if hy else hx) for (_, f, hx, hy), X in zip(probs, xs)]
+    infos = hj.solve_batched(table, rel_tol=1e-8, autotune=True)
+    for i, (kind, f, hx, hy) in enumerate(probs):
+        r = residual_np(kind, f, host(xs[i]), hx, hy if hy else hx)
+        assert infos[i].status == hj.HJ_OK and r <= 1.0001e-8, (i, r)
+    tile, s, ov, us = hj.autotune(2, 512, 512)
+    say(f"autotune 512^2 FP64: tile {tile} s {s} overlap {ov}: {us:.3f} us per sweep")
+    assert ov == (2 * s - 2, 2 * s - 2) and us > 0
+    t1, s1, o1, us1 = hj.autotune(1, 100000)
+    assert o1 == 2 * s1 - 2 and us1 > 0
