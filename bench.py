@@ -107,6 +107,13 @@ def main():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the FP32-cycles + FP64-refinement rows (to 1e-10)")
     ap.add_argument("--mixed-tol", type=float, default=1e-10)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched rows (512 2D + 128 1D problems)")
+    ap.add_argument("--batch-cycles", type=int, default=24,
+                    help="fixed cycles of the batched-vs-one-call-per-problem comparison")
+    ap.add_argument("--batch-cap", type=int, default=2000,
+                    help="cycle cap of the batched solve to --batch-tol")
+    ap.add_argument("--batch-tol", type=float, default=1e-8)
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample budget")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -231,6 +238,10 @@ def main():
 
     if not args.no_mixed:
         extra["mixed_precision"] = mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream)
+    if not args.no_batch:
+        del fs, xs
+        torch.cuda.empty_cache()
+        extra["batched"] = batched_rows(args, torch, hj, stream)
 
     cpu = None
     if not args.no_cpu:
@@ -303,6 +314,94 @@ def mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream):
     out["refined_ms_per_problem"] = round(sum(out["refined_ms"].values()) / len(fs), 3)
     out["speedup_refined_vs_fp64"] = round(out["fp64_ms_per_problem"] / out["refined_ms_per_problem"], 3)
     return out
+
+
+def batched_rows(args, torch, hj, stream):
+    """512 square 2D problems (side log-uniform in [64, 1024]) and 128 1D
+    problems (N log-uniform in [1e3, 1e6]), FP64, random-mode right-hand sides
+    (workloads.batch_specs).  Shapes from the autotuner.  (1) A fixed number of
+    cycles of every problem: one hj_solve_batched call against one
+    hj_solve_2d / hj_solve_1d call per problem (same iterates, checked).
+    (2) The batched solve to --batch-tol with a cycle cap: a few problems hold
+    a mode so smooth that Jacobi needs millions of sweeps, so the cap decides
+    how many converge; the same cap is applied to the per-problem calls."""
+    from paper_2006_16465_amd import workloads as W
+    log("batched: building 512 2D + 128 1D problems")
+    specs = W.batch_specs(0)
+    table = []
+    for spec in specs:
+        F = torch.from_numpy(W.batch_rhs(spec)).to("cuda")
+        table.append((F, torch.zeros_like(F), 1.0 / (spec[1] + 1)))
+    (t2, s2, o2), (t1, s1, o1) = hj.autotune_batch(table)
+    log(f"batched: autotuned 2D tile {t2} s {s2} overlap {o2}; 1D tile {t1} s {s1} overlap {o1}")
+    shape = dict(tile=t2, s=s2, overlap=o2, tile_1d=t1, s_1d=s1, overlap_1d=o1)
+    dof = sum(n * n if d == 2 else n for d, n, _ in specs)
+    sweeps_per_cycle = sum((n * n * s2) if d == 2 else (n * s1) for d, n, _ in specs)
+
+    def clear():
+        for _, x, _ in table:
+            x.zero_()
+        torch.cuda.synchronize()
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        r = fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1), r
+
+    def one_by_one(rel_tol, cap):
+        out = []
+        for F, X, h in table:
+            if F.dim() == 2:
+                out.append(hj.solve_2d(F, X, h, tile=t2, s=s2, overlap=o2, rel_tol=rel_tol, max_cycles=cap,
+                                       allow_not_converged=True))
+            else:
+                out.append(hj.solve_1d(F, X, h, tile=t1, s=s1, overlap=o1, rel_tol=rel_tol, max_cycles=cap,
+                                       allow_not_converged=True))
+        return out
+
+    K = args.batch_cycles
+    clear()
+    hj.solve_batched(table, rel_tol=0.0, max_cycles=2, **shape)  # warm-up (graph, scratch)
+    clear()
+    tb, _ = timed(lambda: hj.solve_batched(table, rel_tol=0.0, max_cycles=K, **shape))
+    xb = [x.clone() for _, x, _ in table]
+    clear()
+    one_by_one(0.0, 2)
+    clear()
+    ts, _ = timed(lambda: one_by_one(0.0, K))
+    same = all(torch.equal(a, x) for a, (_, x, _) in zip(xb, table))
+    del xb
+    log(f"batched: {K} cycles: batched {tb:.1f} ms, one call per problem {ts:.1f} ms, identical {same}")
+
+    C, tol = args.batch_cap, args.batch_tol
+    clear()
+    tt, infos = timed(lambda: hj.solve_batched(table, rel_tol=tol, max_cycles=C, allow_not_converged=True,
+                                               **shape))
+    conv = [i for i in infos if i.status == hj.HJ_OK]
+    clear()
+    tts, infos_s = timed(lambda: one_by_one(tol, C))
+    conv_s = sum(1 for i in infos_s if i.status == hj.HJ_OK)
+    log(f"batched: to {tol:g} (cap {C} cycles): batched {tt:.1f} ms ({len(conv)} of {len(infos)} converged), "
+        f"one call per problem {tts:.1f} ms ({conv_s})")
+    cyc = np.array([i.cycles for i in conv]) if conv else np.array([0])
+    return {
+        "workload": "512 square 2D (side log-uniform [64, 1024]) + 128 1D (N log-uniform [1e3, 1e6]) Poisson "
+                    "problems, FP64, 8 random sine modes each, x0 = 0 (workloads.batch_specs(0))",
+        "dof": int(dof),
+        "shapes": {"2d": {"tile": list(t2), "s": s2, "overlap": list(o2)},
+                   "1d": {"tile": t1, "s": s1, "overlap": o1}, "by": "autotuner (hj_autotune_batch)"},
+        "fixed_cycles": {"cycles": K, "batched_ms": round(tb, 2), "one_call_per_problem_ms": round(ts, 2),
+                         "speedup": round(ts / tb, 2), "identical_iterates": bool(same),
+                         "batched_gsweeps_per_s": round(sweeps_per_cycle * K / (tb * 1e-3) / 1e9, 1)},
+        "to_tol": {"tol": tol, "cycle_cap": C, "batched_ms": round(tt, 2),
+                   "one_call_per_problem_ms": round(tts, 2), "converged": len(conv),
+                   "converged_one_call_per_problem": conv_s, "problems": len(infos),
+                   "cycles_median_converged": float(np.median(cyc)), "cycles_max_converged": int(cyc.max())},
+    }
 
 
 def calibrate_copy(torch):

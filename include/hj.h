@@ -215,7 +215,9 @@ typedef struct hj_batch_params {
 
 /* Scratch: one iterate array per problem (the sum of the problems' sizes),
  * partials and control blocks, kept per device and grown on demand.  infos
- * (nprob entries) may be NULL.  Returns HJ_OK when every problem met rel_tol
+ * (nprob entries) may be NULL; problem i met rel_tol iff
+ * infos[i].rel_residual <= rel_tol (NaN: its residual became non-finite).
+ * Problems must not share x arrays.  Returns HJ_OK when every problem met rel_tol
  * (or ran max_cycles in fixed-count mode), HJ_ERR_NOT_CONVERGED if some
  * stopped at max_cycles (their latest iterate is in x), HJ_ERR_NONFINITE if
  * some residual became non-finite. */
@@ -233,6 +235,14 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
  * and its time per sweep in microseconds.  Results are cached per size. */
 hj_status hj_autotune(int32_t dim, int64_t nx, int64_t ny, hj_dtype dtype, void *stream,
                       hj_params *best, double *us_per_sweep);
+
+/* The cycle shapes hj_solve_batched with HJ_BATCH_AUTOTUNE uses for this
+ * table: hj_autotune on the largest 2D problem with tiles no larger than the
+ * smallest 2D problem (and tile_x <= 64), and on the largest 1D problem.
+ * p2 / p1 may be NULL; a dimension the table lacks leaves its output as
+ * hj_params_default fills it. */
+hj_status hj_autotune_batch(const hj_problem *probs, int64_t nprob, hj_dtype dtype, void *stream,
+                            hj_params *p2, hj_params *p1);
 
 /* Variable-coefficient diffusion -div(a grad u) = f on the 2D grid (the
  * general pentadiagonal Jacobi of Sec. 4 with per-point coefficients), for a

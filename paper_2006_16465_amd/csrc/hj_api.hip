@@ -537,6 +537,33 @@ hj_status autotune_locked(int dim, int64_t nx, int64_t ny, hj_dtype dt, int txma
     return HJ_OK;
 }
 
+// Shapes for a batch: 2D tuned on its largest problem with tiles that fit
+// the smallest (tile_x <= 64, the batched kernel's widths); 1D on its largest.
+hj_status tune_batch_locked(const hj_problem *probs, int64_t nprob, hj_dtype dt, hipStream_t st, int dev,
+                            DevScratch &S, hj_params &P2, hj_params &P1)
+{
+    int64_t min_nx = INT64_MAX, min_ny = INT64_MAX, big2 = -1, big1 = -1;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const hj_problem &q = probs[i];
+        if (q.dim == 2) {
+            min_nx = std::min(min_nx, q.nx);
+            min_ny = std::min(min_ny, q.ny);
+            if (big2 < 0 || q.nx * q.ny > probs[big2].nx * probs[big2].ny) big2 = i;
+        } else if (big1 < 0 || q.nx > probs[big1].nx) {
+            big1 = i;
+        }
+    }
+    hj_status r;
+    double us = 0.0;
+    if (big2 >= 0 &&
+        (r = autotune_locked(2, probs[big2].nx, probs[big2].ny, dt, (int)std::min<int64_t>(min_nx, 64),
+                             (int)std::min<int64_t>(min_ny, 128), st, dev, S, P2, us)) != HJ_OK)
+        return r;
+    if (big1 >= 0 && (r = autotune_locked(1, probs[big1].nx, 1, dt, 1 << 30, 1 << 30, st, dev, S, P1, us)) != HJ_OK)
+        return r;
+    return HJ_OK;
+}
+
 hj_status check_problem(const hj_problem &q, hj_dtype dt, int dev, int64_t i)
 {
     const std::string at = "problem " + std::to_string(i) + ": ";
@@ -896,6 +923,30 @@ hj_status hj_autotune(int32_t dim, int64_t nx, int64_t ny, hj_dtype dtype, void 
     return HJ_OK;
 }
 
+hj_status hj_autotune_batch(const hj_problem *probs, int64_t nprob, hj_dtype dtype, void *stream,
+                            hj_params *p2, hj_params *p1)
+{
+    g_err.clear();
+    if (!probs) return fail(HJ_ERR_INVALID_ARG, "probs is NULL");
+    if (nprob < 1 || nprob > (1 << 24)) return fail(HJ_ERR_INVALID_ARG, "nprob must be in [1, 2^24]");
+    if (dtype != HJ_F64 && dtype != HJ_F32) return fail(HJ_ERR_INVALID_ARG, "unknown dtype");
+    hj_status r;
+    for (int64_t i = 0; i < nprob; ++i)
+        if ((r = check_problem(probs[i], dtype, -1, i)) != HJ_OK) return r;
+    int dev = 0;
+    HJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
+    DevScratch &S = g_scr[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    hj_params P2, P1;
+    hj_params_default(&P2);
+    hj_params_default(&P1);
+    if ((r = tune_batch_locked(probs, nprob, dtype, (hipStream_t)stream, dev, S, P2, P1)) != HJ_OK) return r;
+    if (p2) *p2 = P2;
+    if (p1) *p1 = P1;
+    return HJ_OK;
+}
+
 hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batch_params *p,
                            void *stream, hj_info *infos)
 {
@@ -912,7 +963,7 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
     if (p->flags & ~HJ_BATCH_AUTOTUNE) return fail(HJ_ERR_INVALID_ARG, "unknown bits in flags");
     const bool tune = (p->flags & HJ_BATCH_AUTOTUNE) != 0;
     hj_status r;
-    int64_t n2 = 0, n1 = 0, min_nx = INT64_MAX, min_ny = INT64_MAX, big2 = -1, big1 = -1;
+    int64_t n2 = 0, n1 = 0, min_nx = INT64_MAX, min_ny = INT64_MAX;
     for (int64_t i = 0; i < nprob; ++i) {
         const hj_problem &q = probs[i];
         if ((r = check_problem(q, dt, -1, i)) != HJ_OK) return r;
@@ -920,10 +971,8 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
             ++n2;
             min_nx = std::min(min_nx, q.nx);
             min_ny = std::min(min_ny, q.ny);
-            if (big2 < 0 || q.nx * q.ny > probs[big2].nx * probs[big2].ny) big2 = i;
         } else {
             ++n1;
-            if (big1 < 0 || q.nx > probs[big1].nx) big1 = i;
         }
     }
     if (!tune) {
@@ -953,20 +1002,12 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
     std::lock_guard<std::mutex> lock(S.mu);
     hipStream_t st = (hipStream_t)stream;
     hj_params P2 = p->p2, P1 = p->p1;
-    if (tune) {
-        double us = 0.0;
-        if (n2 && (r = autotune_locked(2, probs[big2].nx, probs[big2].ny, dt, (int)std::min<int64_t>(min_nx, 64),
-                                       (int)std::min<int64_t>(min_ny, 128), st, dev, S, P2, us)) != HJ_OK)
-            return r;
-        if (n1 && (r = autotune_locked(1, probs[big1].nx, 1, dt, 1 << 30, 1 << 30, st, dev, S, P1, us)) != HJ_OK)
-            return r;
-    }
+    if (tune && (r = tune_batch_locked(probs, nprob, dt, st, dev, S, P2, P1)) != HJ_OK) return r;
     const int idt = dt == HJ_F64 ? hj::F64 : hj::F32;
     const size_t es = esize(dt);
 
-    // host tables: problem records, work lists (iso 2D, other 2D, 1D), arena offsets
+    // host tables: problem records and arena offsets
     std::vector<hj::BProb> hp((size_t)nprob);
-    std::vector<int32_t> own_iso, own_gen, own_1d;
     int64_t arena = 0, npart = 0;
     for (int64_t i = 0; i < nprob; ++i) {
         const hj_problem &q = probs[i];
@@ -975,28 +1016,22 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
         b.dim = q.dim;
         b.f = q.f;
         b.x = q.x;
-        int64_t items = 0, elems = 0;
-        std::vector<int32_t> *lst = &own_1d;
+        int64_t elems = 0;
         if (q.dim == 2) {
             b.g2 = make_geom2(q.nx, q.ny, q.ld, q.hx, q.hy, P2);
-            items = (int64_t)b.g2.ntx * b.g2.nty;
+            b.nitems = (int64_t)b.g2.ntx * b.g2.nty;
             elems = q.ny * q.ld;
-            lst = b.g2.iso ? &own_iso : &own_gen;
         } else {
             b.g1 = make_geom1(q.nx, q.hx, &P1);
-            items = hj::cycle1d_blocks(b.g1);
+            b.nitems = hj::cycle1d_blocks(b.g1);
             elems = q.nx;
         }
-        b.item0 = (int64_t)lst->size();
-        b.nitems = items;
         b.part0 = npart;
-        npart += items;
-        lst->insert(lst->end(), (size_t)items, (int32_t)i);
+        npart += b.nitems;
         b.s1 = (void *)(intptr_t)arena;  // offset; rebased below
         arena += ((int64_t)elems * (int64_t)es + 255) / 256 * 256;
     }
-    const int64_t nown = (int64_t)(own_iso.size() + own_gen.size() + own_1d.size());
-    if (nown > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "batch too large");
+    if (npart > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "batch too large");
 
     BatchScratch &B = g_bat[dev];
     if (!B.cap) HJ_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
@@ -1012,7 +1047,7 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
         B.arena_bytes = have;
     }
     if ((r = grow_dev(B.probs, B.nprobs, nprob)) != HJ_OK) return r;
-    if ((r = grow_dev(B.owner, B.nowner, std::max<int64_t>(nown, 1))) != HJ_OK) return r;
+    if ((r = grow_dev(B.owner, B.nowner, std::max<int64_t>(npart, 1))) != HJ_OK) return r;
     if ((r = grow_dev(B.part, B.npart, 2 * npart)) != HJ_OK) return r;
     if ((r = grow_dev(B.ctrl, B.nctrl, nprob)) != HJ_OK) return r;
     if (nprob > B.nhost) {
@@ -1023,52 +1058,72 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
         B.nhost = nprob;
     }
     for (auto &b : hp) b.s1 = (char *)B.arena + (intptr_t)b.s1;
-    std::vector<int32_t> own;
-    own.reserve((size_t)nown);
-    own.insert(own.end(), own_iso.begin(), own_iso.end());
-    own.insert(own.end(), own_gen.begin(), own_gen.end());
-    own.insert(own.end(), own_1d.begin(), own_1d.end());
-    HJ_HIP(hipMemcpyAsync(B.probs, hp.data(), hp.size() * sizeof(hj::BProb), hipMemcpyHostToDevice, st));
-    if (nown) HJ_HIP(hipMemcpyAsync(B.owner, own.data(), own.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     const double tol = p->rel_tol > 0.0 ? p->rel_tol : -1.0;
     HJ_HIP(hj::launch_batch_init(B.ctrl, (int)nprob, B.bc, p->max_cycles, tol, st));
-    HJ_HIP(hipStreamSynchronize(st));  // host tables may go out of scope after this
 
-    // capture a fixed run of cycles; the cycle index lives on the device
+    // Work lists of the problems still running (iso 2D, other 2D, 1D, in that
+    // order in one owner array; a problem's items stay contiguous), uploaded
+    // with the updated problem records, and a fixed run of K cycles captured
+    // on them.  Rebuilt when the running problems hold under half of the
+    // listed items, so the tail of long-running problems does not pay for
+    // launching everyone else's finished tiles.  The caller's stream is idle
+    // whenever this runs.
     const int K = p->graph_cycles ? p->graph_cycles : 8;
-    const hj::BatchLaunch Li{B.probs, B.owner, (int64_t)own_iso.size(), B.bc, B.ctrl, B.part, npart, P2.s};
-    const hj::BatchLaunch Lg{B.probs, B.owner + own_iso.size(), (int64_t)own_gen.size(), B.bc, B.ctrl,
-                             B.part, npart, P2.s};
-    const hj::BatchLaunch L1{B.probs, B.owner + own_iso.size() + own_gen.size(), (int64_t)own_1d.size(),
-                             B.bc, B.ctrl, B.part, npart, P1.s};
+    std::vector<int32_t> own;
+    int64_t n_iso = 0, n_gen = 0, n_1d = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    HJ_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = hipSuccess;
-    for (int k = 0; k < K && ce == hipSuccess; ++k) {
-        if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, true, Li, B.cap);
-        if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, false, Lg, B.cap);
-        if (ce == hipSuccess) ce = hj::launch_batch_cycle1d(idt, P1.tile_x, L1, B.cap);
-        if (ce == hipSuccess) ce = hj::launch_batch_judge(B.probs, (int)nprob, B.bc, B.ctrl, B.part, npart, B.cap);
-        if (ce == hipSuccess) ce = hj::launch_batch_advance(B.bc, B.cap);
-    }
-    const hipError_t ee = hipStreamEndCapture(B.cap, &graph);
-    if (ce != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return hip_fail(ce, "capturing the batch cycle");
-    }
-    HJ_HIP(ee);
-    {
-        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (ie != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return hip_fail(ie, "hipGraphInstantiate");
-        }
-    }
     auto cleanup = [&]() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
     };
+    auto rebuild = [&](const hj::Ctrl *snap) -> hj_status {
+        own.clear();
+        for (int pass = 0; pass < 3; ++pass) {
+            const int64_t start = (int64_t)own.size();
+            for (int64_t i = 0; i < nprob; ++i) {
+                hj::BProb &b = hp[(size_t)i];
+                const int kind = b.dim == 1 ? 2 : (b.g2.iso ? 0 : 1);
+                if (kind != pass || (snap && snap[i].status != hj::ST_RUNNING)) continue;
+                b.item0 = (int64_t)own.size() - start;
+                own.insert(own.end(), (size_t)b.nitems, (int32_t)i);
+            }
+            (pass == 0 ? n_iso : pass == 1 ? n_gen : n_1d) = (int64_t)own.size() - start;
+        }
+        HJ_HIP(hipMemcpyAsync(B.probs, hp.data(), hp.size() * sizeof(hj::BProb), hipMemcpyHostToDevice, st));
+        if (!own.empty())
+            HJ_HIP(hipMemcpyAsync(B.owner, own.data(), own.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HJ_HIP(hipStreamSynchronize(st));  // the host tables change on the next rebuild
+        cleanup();
+        const hj::BatchLaunch Li{B.probs, B.owner, n_iso, B.bc, B.ctrl, B.part, npart, P2.s};
+        const hj::BatchLaunch Lg{B.probs, B.owner + n_iso, n_gen, B.bc, B.ctrl, B.part, npart, P2.s};
+        const hj::BatchLaunch L1{B.probs, B.owner + n_iso + n_gen, n_1d, B.bc, B.ctrl, B.part, npart, P1.s};
+        HJ_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int k = 0; k < K && ce == hipSuccess; ++k) {
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, true, Li, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, false, Lg, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle1d(idt, P1.tile_x, L1, B.cap);
+            if (ce == hipSuccess)
+                ce = hj::launch_batch_judge(B.probs, (int)nprob, B.bc, B.ctrl, B.part, npart, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_advance(B.bc, B.cap);
+        }
+        const hipError_t ee = hipStreamEndCapture(B.cap, &graph);
+        if (ce != hipSuccess) {
+            cleanup();
+            return hip_fail(ce, "capturing the batch cycle");
+        }
+        HJ_HIP(ee);
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            cleanup();
+            return hip_fail(ie, "hipGraphInstantiate");
+        }
+        return HJ_OK;
+    };
+    if ((r = rebuild(nullptr)) != HJ_OK) return r;
 
     // replay with one replay of lookahead; poll the control blocks in between
     const int64_t replays = (p->max_cycles + 1 + K - 1) / K;  // cycles 0 .. max_cycles
@@ -1088,10 +1143,23 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
         const bool more = launched < replays;
         if (more && (le = enqueue(slot ^ 1)) != hipSuccess) break;
         if ((le = hipEventSynchronize(S.ev[slot])) != hipSuccess) break;
-        bool running = false;
-        for (int64_t i = 0; i < nprob && !running; ++i)
-            running = B.host[(size_t)slot * nprob + i].status == hj::ST_RUNNING;
-        if (!running || !more) break;
+        const hj::Ctrl *snap = B.host + (size_t)slot * nprob;
+        int64_t live_items = 0;
+        for (int64_t i = 0; i < nprob; ++i)
+            if (snap[i].status == hj::ST_RUNNING) live_items += hp[(size_t)i].nitems;
+        if (live_items == 0 || !more) break;
+        if (2 * live_items < (int64_t)own.size()) {
+            // drain the lookahead replay, then rebuild from its newer snapshot
+            if ((le = hipEventSynchronize(S.ev[slot ^ 1])) != hipSuccess) break;
+            if ((r = rebuild(B.host + (size_t)(slot ^ 1) * nprob)) != HJ_OK) {
+                cleanup();
+                return r;
+            }
+            if (launched >= replays) break;
+            if ((le = enqueue(0)) != hipSuccess) break;
+            slot = 0;
+            continue;
+        }
         slot ^= 1;
     }
     if (le == hipSuccess) le = hj::launch_batch_finalize(idt, B.probs, (int)nprob, B.ctrl, st);

@@ -111,7 +111,7 @@ class HJError(RuntimeError):
 
 _lib = None
 EXPORTS = ("hj_params_default", "hj_solve_1d", "hj_solve_2d", "hj_solve_2d_refined", "hj_residual",
-           "hj_solve_batched", "hj_autotune", "hj_solve_vc_2d", "hj_vc_grad_a", "hj_solve_adjoint",
+           "hj_solve_batched", "hj_autotune", "hj_autotune_batch", "hj_solve_vc_2d", "hj_vc_grad_a", "hj_solve_adjoint",
            "hj_axis_tiles",
            "hj_status_string", "hj_last_error", "hj_version")
 
@@ -141,6 +141,8 @@ def load():
     lib.hj_solve_batched.restype = i32
     lib.hj_autotune.argtypes = [i32, i64, i64, i32, vp, P, ctypes.POINTER(f64)]
     lib.hj_autotune.restype = i32
+    lib.hj_autotune_batch.argtypes = [ctypes.POINTER(Problem), i64, i32, vp, P, P]
+    lib.hj_autotune_batch.restype = i32
     lib.hj_solve_vc_2d.argtypes = [ctypes.POINTER(VCProblem), vp, vp, P, vp, I]
     lib.hj_solve_vc_2d.restype = i32
     lib.hj_vc_grad_a.argtypes = [ctypes.POINTER(VCProblem), vp, vp, vp, i64, vp]
@@ -292,19 +294,8 @@ def solve_2d_refined(f, x, h=None, *, hx=None, hy=None, tile=(64, 32), s=8, over
     raise HJError(st, last_error())
 
 
-def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 18), tile_1d=256,
-                  s_1d=16, overlap_1d=30, max_cycles=1_000_000, graph_cycles=8, autotune=False,
-                  allow_not_converged=False) -> list:
-    """Solve many independent problems together (hj_solve_batched).
-
-    problems: sequence of (f, x, h) or (f, x, hx, hy); f, x GPU tensors of one
-    dtype, shape (n,) for 1D and (ny, nx) for 2D (row-major).  Each x is updated
-    in place.  2D problems use the cycle (tile, s, overlap), 1D problems
-    (tile_1d, s_1d, overlap_1d); autotune=True lets the library choose both.
-    Returns one Info per problem."""
-    import torch
-    if not problems:
-        return []
+def _problem_table(problems):
+    """ctypes array of Problem for (f, x, h) / (f, x, hx, hy) entries, and the dtype code."""
     arr = (Problem * len(problems))()
     dt = None
     for i, pr in enumerate(problems):
@@ -332,6 +323,36 @@ def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 1
             q.dim, q.ny, q.nx, q.ld = 2, f.shape[0], f.shape[1], ld
         else:
             raise ValueError("problems are 1D or 2D tensors")
+    return arr, dt
+
+
+def autotune_batch(problems):
+    """Cycle shapes hj_solve_batched(autotune=True) would use for this table:
+    ((tile, s, overlap) for 2D, (tile, s, overlap) for 1D)."""
+    arr, dt = _problem_table(problems)
+    p2, p1 = Params(), Params()
+    f0 = problems[0][0]
+    with _device(f0):
+        st = load().hj_autotune_batch(arr, len(problems), dt, _stream(f0), ctypes.byref(p2), ctypes.byref(p1))
+    if st != HJ_OK:
+        raise HJError(st, last_error())
+    return ((p2.tile_x, p2.tile_y), p2.s, (p2.overlap_x, p2.overlap_y)), (p1.tile_x, p1.s, p1.overlap_x)
+
+
+def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 18), tile_1d=256,
+                  s_1d=16, overlap_1d=30, max_cycles=1_000_000, graph_cycles=8, autotune=False,
+                  allow_not_converged=False) -> list:
+    """Solve many independent problems together (hj_solve_batched).
+
+    problems: sequence of (f, x, h) or (f, x, hx, hy); f, x GPU tensors of one
+    dtype, shape (n,) for 1D and (ny, nx) for 2D (row-major).  Each x is updated
+    in place.  2D problems use the cycle (tile, s, overlap), 1D problems
+    (tile_1d, s_1d, overlap_1d); autotune=True lets the library choose both.
+    Returns one Info per problem."""
+    import torch
+    if not problems:
+        return []
+    arr, dt = _problem_table(problems)
     bp = BatchParams()
     bp.p2 = make_params(tile, s, "hierarchical", rel_tol, max_cycles, 0, overlap)
     bp.p1 = make_params(tile_1d, s_1d, "hierarchical", rel_tol, max_cycles, 0, overlap_1d)
@@ -346,7 +367,17 @@ def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 1
         st = load().hj_solve_batched(arr, len(problems), ctypes.byref(bp), _stream(f0), infos)
     if st != HJ_OK and not (st == HJ_ERR_NOT_CONVERGED and allow_not_converged):
         raise HJError(st, last_error())
-    return [Info(st, i.cycles, i.sweeps, i.rel_residual, i.r0_norm) for i in infos]
+    out = []
+    for i in infos:
+        # per problem, as the device judged it: met rel_tol, went non-finite, or ran out of cycles
+        if i.rel_residual != i.rel_residual:
+            ps = HJ_ERR_NONFINITE
+        elif rel_tol > 0.0 and i.rel_residual > rel_tol:
+            ps = HJ_ERR_NOT_CONVERGED
+        else:
+            ps = HJ_OK
+        out.append(Info(ps, i.cycles, i.sweeps, i.rel_residual, i.r0_norm))
+    return out
 
 
 def autotune(dim, nx, ny=1, dtype=None):

@@ -95,6 +95,29 @@ def rhs_random(shape, seed: int = 0) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(shape)
 
 
+def batch_specs(seed: int = 0, n2d: int = 512, n1d: int = 128, side=(64, 1024),
+                n1=(1_000, 1_000_000)):
+    """The batched workload: n2d square 2D grids with side log-uniform in
+    [side[0], side[1]] and n1d 1D grids with N log-uniform in [n1[0], n1[1]]
+    (sizes drawn from default_rng(seed), 2D sides first, then 1D sizes).
+    Returns (dim, n, rhs_seed) per problem: problem i's right-hand side is
+    rhs_2d_modes(n, n, 8, 0, rhs_seed) or rhs_1d_modes(n, 8, rhs_seed), with
+    rhs_seed = 1_000_003 * seed + i, so one problem can be rebuilt alone."""
+    rng = np.random.default_rng(seed)
+    sides = np.exp(rng.uniform(np.log(side[0]), np.log(side[1]), n2d)).astype(np.int64)
+    ns = np.exp(rng.uniform(np.log(n1[0]), np.log(n1[1]), n1d)).astype(np.int64)
+    sides = np.clip(sides, side[0], side[1])
+    ns = np.clip(ns, n1[0], n1[1])
+    out = [(2, int(n), 1_000_003 * seed + i) for i, n in enumerate(sides)]
+    out += [(1, int(n), 1_000_003 * seed + n2d + i) for i, n in enumerate(ns)]
+    return out
+
+
+def batch_rhs(spec) -> np.ndarray:
+    dim, n, sd = spec
+    return rhs_2d_modes(n, n, 8, 0.0, sd) if dim == 2 else rhs_1d_modes(n, 8, sd)
+
+
 # Named workloads.  "tile" is (tile_x, tile_y) in 2D, an int in 1D.
 CONFIGS = {
     # 1D Poisson, N = 256, 8 random sine modes, tile 32, s = 16, to 1e-6

@@ -98,6 +98,7 @@ def test_batch_not_converged_keeps_last_iterate(orc):
     probs = make_batch(2)
     got, infos = gpu_batch(probs, rel_tol=1e-12, max_cycles=4, allow_not_converged=True)
     assert any(i.status == hj.HJ_ERR_NOT_CONVERGED for i in infos)
+    assert all((i.status == hj.HJ_OK) == (i.rel_residual <= 1e-12) for i in infos)
     for i, (kind, f, hx, hy) in enumerate(probs):
         c = infos[i].cycles
         assert 0 <= c <= 4
@@ -119,6 +120,17 @@ def test_batch_fp32_within_1e5_of_fp64_oracle(orc):
         else:
             want = orc.hier_1d(f, np.zeros_like(f), hx, T1, S1, 12, O1)
         assert np.linalg.norm(got[i] - want) <= 1e-5 * np.linalg.norm(want)
+
+
+def test_batch_compaction_keeps_results(orc):
+    """Problems converging at very different cycle counts: the work lists are
+    rebuilt as problems stop (graph re-captured), results unchanged."""
+    probs = make_batch(0)  # 1D problem 8 needs 5668 cycles, the rest at most 114
+    got, infos = gpu_batch(probs, rel_tol=1e-8, graph_cycles=4)
+    for i, pr in enumerate(probs):
+        xo, co, _, _ = oracle_solve(orc, pr, 1e-8)
+        assert infos[i].status == hj.HJ_OK and infos[i].cycles == co
+        assert np.array_equal(got[i], xo)
 
 
 def test_batch_equals_single_problem_solves():
