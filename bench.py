@@ -33,7 +33,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_2006_16465_amd", "csrc", "hj_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2006_16465_amd", "csrc", name)
+              for name in ("hj_kernels.hip", "hj_tiles.h", "hj_device.h")]
 
 
 def log(*a):
@@ -71,8 +72,12 @@ def cycle_kernel_name(tile, n):
 
 
 def kernel_source_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the sources that define the cycle and sweep kernels."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic(name):
