@@ -58,7 +58,7 @@ __global__ __launch_bounds__(64 * W) void k_batch_cycle2d(const BProb *__restric
     const T *xin = (const T *)((c & 1) ? P.s1 : P.x);
     T *xout = (T *)((c & 1) ? P.x : P.s1);
     const int tile = (int)(w - P.item0);
-    const double rsq = reg_tile_2d<T, C, R, W, true, ISO>(P.g2, tile, f, xin, xout, s);
+    const double rsq = reg_tile_2d<T, C, R, W, true, ISO, rotate_rows<T>()>(P.g2, tile, f, xin, xout, s);
     post_partial_at<NT>(rsq, &pc[P.part0 + tile]);
 }
 

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(64 * W) void k_cycle2d_reg(Geom2 g, const T *__rest
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<NT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
-    const double rsq = reg_tile_2d<T, C, R, W, RES, ISO>(g, xcd_tile(blockIdx.x, gridDim.x), f, xin,
+    const double rsq = reg_tile_2d<T, C, R, W, RES, ISO, rotate_rows<T>()>(g, xcd_tile(blockIdx.x, gridDim.x), f, xin,
                                                          xout, nsub);
     if (RES) post_partial<NT>(rsq, red.part_cur);
 }

@@ -7,11 +7,23 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "hj_launch.h"
 
 namespace hj {
 namespace {
+
+// Rows in R + 1 rotating register slots (no register moves, straight-line
+// rounds of R + 1 sweeps) or updated in place (one move per point and sweep).
+// Measured at 4096^2: rotation costs FP64 about 34 VGPRs and one wave per
+// SIMD (64x128: 236 against 183 us per cycle) but saves FP32 about a tenth
+// (89 against 98 us), where the registers are half the size.
+template <typename T>
+constexpr bool rotate_rows()
+{
+    return sizeof(T) == 4;
+}
 
 // ---------------------------------------------------------------- updates
 // 2D: iso  -> (h^2 f + ((W + E) + (S + N))) * 0.25      (Sec. 4.2, dx == dy)
@@ -103,7 +115,7 @@ __device__ __forceinline__ float fma_quarter(float sv, float b)
 // workgroup of 64 W threads.  Returns this thread's share of ||r||^2 of xin
 // over the owned points (RES), else 0.  A caller that runs several tiles in a
 // row must place a barrier between them (LDS is reused).
-template <typename T, int C, int R, int W, bool RES, bool ISO>
+template <typename T, int C, int R, int W, bool RES, bool ISO, bool ROT>
 __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T *__restrict__ f,
                                               const T *__restrict__ xin, T *__restrict__ xout,
                                               int nsub)
@@ -121,8 +133,9 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
     const int lr0 = k * R, lc0 = j * C;
     const int64_t base = (int64_t)(r0 + lr0) * ld + c0 + lc0;
 
-    // step 1: tile, halo and f into registers / LDS
-    T x[R][C], bq[R][C], hw[R], he[R];
+    // step 1: tile, halo and f into registers / LDS (phase 0: row i in slot i)
+    constexpr int NS = ROT ? R + 1 : R;
+    T x[NS][C], bq[R][C], hw[R], he[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
 #pragma unroll
@@ -155,11 +168,11 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
     // fetch the neighbouring groups' (or the frozen halo rows).  A buffer is
     // rewritten two sweeps later, after a barrier that every thread reaches
     // only once its reads from it are done.
-    auto exchange = [&](int par) {
+    auto exchange = [&]<int P>(int par) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            s_top[par][k][lc0 + c] = x[0][c];
-            s_bot[par][k][lc0 + c] = x[R - 1][c];
+            s_top[par][k][lc0 + c] = x[P % NS][c];
+            s_bot[par][k][lc0 + c] = x[(R - 1 + P) % NS][c];
         }
         __syncthreads();
         const T *pu = k == 0 ? &s_halo[0][lc0] : &s_bot[par][k - 1][lc0];
@@ -171,12 +184,98 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
         }
     };
 
+    double rsq = 0.0;
+    const T hh = T(g.hh);
+    if constexpr (ROT) {
+    // One sub-iteration at phase P: row i of the lane sits in slot (i + P) mod NS
+    // and its new value goes to the slot of row i - 1 (free once new row i is
+    // formed; for row 0 the spare slot), so the sweep leaves phase P - 1 and
+    // moves no registers.  FIRST: bq still holds f; it also accumulates the
+    // residual of the incoming iterate over the owned points and scales f
+    // (h^2 f / 4 when isotropic) as it goes.
+    auto sweep = [&]<int P, bool FIRST>() {
+        T above[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) above[c] = up[c];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int cur = (i + P) % NS;
+            const int dst = (i + P + NS - 1) % NS;
+            const T wl = dpp_shift<kDppRowShr1>(x[cur][C - 1]);
+            const T er = dpp_shift<kDppRowShl1>(x[cur][0]);
+            T nw[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const T w = c > 0 ? x[cur][c - 1] : wl;
+                const T e = c < C - 1 ? x[cur][c + 1] : er;
+                T we = w + e;
+                // the halo registers are 0 except in the first / last lane of a
+                // DPP row, where the shifted value is 0: the sum stays W + E
+                if (c == 0) we = we + hw[i];
+                if (c == C - 1) we = we + he[i];
+                const T below = i < R - 1 ? x[(i + 1 + P) % NS][c] : dn[c];
+                const T sn = above[c] + below;
+                if (FIRST) {
+                    if (RES && i >= rlo && i < rhi && c >= clo && c < chi) {
+                        const double wa = c > 0 ? (double)w : (double)wl + (double)hw[i];
+                        const double ea = c < C - 1 ? (double)e : (double)er + (double)he[i];
+                        const double rr = res2((double)bq[i][c], (double)x[cur][c], wa, ea,
+                                               (double)above[c], (double)below, g.wx, g.wy);
+                        rsq += rr * rr;
+                    }
+                    if (ISO) bq[i][c] = (hh * bq[i][c]) * T(0.25);
+                }
+                if (ISO) nw[c] = fma_quarter(we + sn, bq[i][c]);
+                else nw[c] = (bq[i][c] + (wx * we + wy * sn)) * dinv;
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                above[c] = x[cur][c];
+                x[dst][c] = nw[c];
+            }
+        }
+    };
+    auto step = [&]<int P>(int it) {
+        exchange.template operator()<P>(it & 1);
+        sweep.template operator()<P, false>();
+    };
+
+    // step 2: nsub sub-iterations with the halo frozen.  The first runs at
+    // phase 0 and leaves phase NS - 1; full rounds of NS sweeps (phases
+    // NS - 1 .. 0, straight-line code) return there; each remainder sweep
+    // lowers the phase by one.
+    exchange.template operator()<0>(0);
+    sweep.template operator()<0, true>();
+    int it = 1;
+    for (; it + NS <= nsub; it += NS) {
+        [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
+            (step.template operator()<NS - 1 - Ps>(it + Ps), ...);
+        }(std::make_integer_sequence<int, NS>{});
+    }
+    const int rem = nsub - it;  // 0 <= rem < NS
+    [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
+        ((rem > Ps ? (step.template operator()<NS - 1 - Ps>(it + Ps), 0) : 0), ...);
+    }(std::make_integer_sequence<int, NS - 1>{});
+    const int ph = NS - 1 - rem;
+
+    // step 3: owned points back to global memory (row i in slot (i + ph) mod NS)
+    [&]<int... Ps>(std::integer_sequence<int, Ps...>) {
+        ((ph == Ps ? ([&] {
+#pragma unroll
+              for (int i = 0; i < R; ++i)
+#pragma unroll
+                  for (int c = 0; c < C; ++c)
+                      if (i >= rlo && i < rhi && c >= clo && c < chi)
+                          xout[base + (int64_t)i * ld + c] = x[(i + Ps) % NS][c];
+          }(), 0) : 0),
+         ...);
+    }(std::make_integer_sequence<int, NS>{});
+
+    } else {
     // One sub-iteration over the lane's rows, top to bottom, in place: prev
     // keeps the old row above.  FIRST: bq still holds f; it also accumulates
     // the residual of the incoming iterate over the owned points and scales f
     // (h^2 f / 4 when isotropic) as it goes.
-    double rsq = 0.0;
-    const T hh = T(g.hh);
     auto sweep = [&](auto first_tag) {
         constexpr bool FIRST = decltype(first_tag)::value;
         T prev[C];
@@ -220,10 +319,10 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
     };
 
     // step 2: nsub sub-iterations with the halo frozen
-    exchange(0);
+    exchange.template operator()<0>(0);
     sweep(std::true_type{});
     for (int it = 1; it < nsub; ++it) {
-        exchange(it & 1);
+        exchange.template operator()<0>(it & 1);
         sweep(std::false_type{});
     }
 
@@ -234,6 +333,7 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
         for (int c = 0; c < C; ++c)
             if (i >= rlo && i < rhi && c >= clo && c < chi) xout[base + (int64_t)i * ld + c] = x[i][c];
 
+    }
     return rsq;
 }
 

@@ -120,6 +120,20 @@ def test_register_and_lds_kernels_match_oracle(orc, tile, overlap):
         assert np.array_equal(got_lds, want), "LDS kernel"
 
 
+@pytest.mark.parametrize("tile", [(32, 32), (64, 32), (64, 64), (32, 64)])
+def test_fp32_register_kernel_equals_fp32_lds_kernel(tile):
+    """FP32 register tiles rotate rows through R + 1 slots in straight-line
+    rounds of R + 1 sweeps with a remainder; the LDS kernel forms the same
+    sums in the same order, so the two agree bit for bit for every s."""
+    ny, nx = 150, 200
+    f = W.rhs_random((ny, nx), 9)
+    x0 = W.rhs_random((ny, nx), 10)
+    for s, ov in ((1, (0, 0)), (2, (2, 2)), (3, (4, 4)), (5, (8, 8)), (7, (0, 0)), (9, (12, 12)), (12, (6, 6))):
+        a, _ = gpu_cycles_2d(f, x0, 1.0 / 201, tile, s, 3, ov, dtype=torch.float32)
+        b, _ = gpu_cycles_2d(f, x0, 1.0 / 201, tile, s, 3, ov, dtype=torch.float32, lds_kernel=True)
+        assert np.array_equal(a, b), (tile, s, ov)
+
+
 @pytest.mark.parametrize("tile", [(32, 64), (32, 128), (64, 64), (64, 128), (128, 16), (128, 32),
                                   (128, 64), (128, 128)])
 @pytest.mark.parametrize("overlap", [(0, 0), (14, 14), (30, 6)])
