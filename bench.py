@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--batch-cap", type=int, default=2000,
                     help="cycle cap of the batched solve to --batch-tol")
     ap.add_argument("--batch-tol", type=float, default=1e-8)
+    ap.add_argument("--no-diffusion", action="store_true",
+                    help="skip the variable-coefficient / adjoint rows")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample budget")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -247,6 +249,8 @@ def main():
         del fs, xs
         torch.cuda.empty_cache()
         extra["batched"] = batched_rows(args, torch, hj, stream)
+    if not args.no_diffusion:
+        extra["differentiable"] = diffusion_rows(torch, hj, stream)
 
     cpu = None
     if not args.no_cpu:
@@ -407,6 +411,96 @@ def batched_rows(args, torch, hj, stream):
                    "converged_one_call_per_problem": conv_s, "problems": len(infos),
                    "cycles_median_converged": float(np.median(cyc)), "cycles_max_converged": int(cyc.max())},
     }
+
+
+def diffusion_rows(torch, hj, stream):
+    """Variable-coefficient diffusion -div(a grad u) = f, a = exp(g) with g a
+    squared-exponential Gaussian random field (length 0.05, variance 1).
+    (1) Cycle throughput of the VC kernel at 1024^2 (fixed cycles, one RHS).
+    (2) The autograd pipeline at 64^2 with 16 right-hand sides: forward solve
+    to 1e-10, loss mean (u - t)^2 with t smooth, backward = adjoint solve to
+    1e-10 and dL/da, dL/df.  (3) Central differences (eps 1e-6, FP64) of the
+    loss on 32 entries of a and 8 of f at 32^2 with 2 right-hand sides.  The
+    1024^2 solves to 1e-10 are out of reach for any Jacobi-type iteration when
+    the adjoint right-hand side is smooth, hence the smaller grids for (2)/(3)."""
+    from paper_2006_16465_amd import workloads as W
+    out = {}
+    shape = dict(tile=(64, 32), s=8, overlap=(14, 14))
+    log("differentiable: VC cycle throughput at 1024^2")
+    n = 1024
+    h = 1.0 / (n + 1)
+    a = torch.from_numpy(W.diffusion_coefficient(n, 0.05, 1.0, 7)).cuda()
+    f = torch.from_numpy(W.rhs_2d_modes(n, n, 8, 0.0, 0)).cuda()[None]
+    u = torch.zeros_like(f)
+    hj.solve_vc_2d(a, f, u, h, rel_tol=0.0, max_cycles=4, **shape)
+    K = 40
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    u.zero_()
+    e0.record(stream)
+    hj.solve_vc_2d(a, f, u, h, rel_tol=0.0, max_cycles=K, **shape)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / K
+    out["vc_cycle_1024"] = {"tile": list(shape["tile"]), "s": shape["s"], "overlap": list(shape["overlap"]),
+                            "us_per_cycle": round(us, 1), "gsweeps_per_s": round(n * n * shape["s"] / us / 1e3, 1)}
+
+    def pipeline(n, batch, tol, seed):
+        h = 1.0 / (n + 1)
+        a0 = torch.from_numpy(W.diffusion_coefficient(n, 0.05, 1.0, seed)).cuda()
+        f0 = torch.from_numpy(np.stack([W.rhs_2d_modes(n, n, 8, 0.0, seed + b) for b in range(batch)])).cuda()
+        t = torch.from_numpy(np.stack([W.smooth_modes_2d(n, 3, 3, seed + b) for b in range(batch)]) * 1e-3).cuda()
+        return h, a0, f0, t
+
+    log("differentiable: forward + adjoint at 64^2, 16 right-hand sides")
+    h, a0, f0, t = pipeline(64, 16, 1e-10, 11)
+    opts = dict(h=h, rel_tol=1e-10, **shape)
+    A = a0.clone().requires_grad_(True)
+    F = f0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U = hj.diffusion_solve(F, A, **opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss = torch.mean((U - t) ** 2)
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["pipeline_64"] = {"batch": 16, "tol": 1e-10, "forward_ms": round((t1 - t0) * 1e3, 1),
+                          "backward_ms": round((t2 - t1) * 1e3, 1),
+                          "grad_a_norm": float(A.grad.norm()), "grad_f_norm": float(F.grad.norm())}
+
+    log("differentiable: central differences at 32^2 on 32 entries of a and 8 of f")
+    h, a0, f0, t = pipeline(32, 2, 1e-13, 21)
+    opts = dict(h=h, rel_tol=1e-13, **{**shape, "tile": (32, 32), "overlap": (14, 14)})
+    A = a0.clone().requires_grad_(True)
+    F = f0.clone().requires_grad_(True)
+    torch.mean((hj.diffusion_solve(F, A, **opts) - t) ** 2).backward()
+    ga, gf = A.grad.cpu().numpy(), F.grad.cpu().numpy()
+    rng = np.random.default_rng(0)
+    eps = 1e-6
+    err_a, err_f = 0.0, 0.0
+    with torch.no_grad():
+        def loss_of(aa, ff):
+            return torch.mean((hj.diffusion_solve(ff, aa, **opts) - t) ** 2).item()
+        for _ in range(32):
+            r, q = rng.integers(0, 34), rng.integers(0, 34)
+            ap, am = a0.clone(), a0.clone()
+            ap[r, q] += eps
+            am[r, q] -= eps
+            fd = (loss_of(ap, f0) - loss_of(am, f0)) / (2 * eps)
+            err_a = max(err_a, abs(fd - ga[r, q]))
+        for _ in range(8):
+            b, r, q = rng.integers(0, 2), rng.integers(0, 32), rng.integers(0, 32)
+            fp, fm = f0.clone(), f0.clone()
+            fp[b, r, q] += eps
+            fm[b, r, q] -= eps
+            fd = (loss_of(a0, fp) - loss_of(a0, fm)) / (2 * eps)
+            err_f = max(err_f, abs(fd - gf[b, r, q]))
+    out["finite_differences_32"] = {"entries_a": 32, "entries_f": 8, "eps": eps,
+                                    "max_err_a_rel_to_max_grad": float(err_a / np.abs(ga).max()),
+                                    "max_err_f_rel_to_max_grad": float(err_f / np.abs(gf).max())}
+    log(f"differentiable: {out}")
+    return out
 
 
 def calibrate_copy(torch):
