@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--batch-tol", type=float, default=1e-8)
     ap.add_argument("--no-diffusion", action="store_true",
                     help="skip the variable-coefficient / adjoint rows")
-    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--inner-tol", type=float, default=1e-6)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample budget")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")

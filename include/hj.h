@@ -138,11 +138,15 @@ hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, 
  * refinement.  f, x: FP64 (x in/out, ld as in hj_solve_2d).
  *
  * Phase 1 runs FP64 cycles (inner's tile, overlap, s, method) on x until the
- * relative residual is <= switch_tol.  Phase 2 repeats refinement steps: form
+ * relative residual is <= switch_tol and keeps the iterate one cycle past
+ * that one (already computed while the verdict was reached).
+ * Phase 2 repeats refinement steps: form
  * r = f - A x in FP64 (stored as FP32), solve A e = r from e = 0 with FP32
  * cycles, accumulate x += e in FP64.  A step's FP32 solve stops when its
- * residual is <= max(inner.rel_tol * ||r||, rel_tol * ||r_0|| / 2), so it
- * never works below what the outer tolerance needs; inner.max_cycles caps it.
+ * residual is <= max(inner.rel_tol * ||r||, rel_tol * ||r_0|| / 2), likewise
+ * handing over one cycle more: the second term stops it once the outer
+ * tolerance is met (with a factor 2 to spare), the first bounds what one step
+ * asks of FP32 (1e-6 is a good choice); inner.max_cycles caps it.
  * The solve stops when the FP64 residual meets rel_tol.
  *
  * The cycle is a consistent stationary iteration, so restarting it on the
@@ -163,8 +167,8 @@ typedef struct hj_refine_params {
 
 typedef struct hj_refine_info {
     int64_t outer;         /* refinement steps taken */
-    int64_t inner_cycles;  /* FP32 cycles over all steps */
-    int64_t fp64_cycles;   /* FP64 cycles of phase 1 */
+    int64_t inner_cycles;  /* FP32 cycles over all steps (iterates handed over, as above) */
+    int64_t fp64_cycles;   /* FP64 cycles of phase 1 (index of the iterate handed over) */
     double rel_residual;   /* final FP64 relative residual */
     double r0_norm;        /* ||f - A x_0||_2 */
 } hj_refine_info;

@@ -180,8 +180,12 @@ hj_status read_ctrl(DevScratch &S, hipStream_t stream, hj::Ctrl &c)
     return HJ_OK;
 }
 
+// latest: in tolerance mode, hand back iterate c + 1 instead of the first
+// iterate c that met the tolerance: it is whole (see stopped()) and one cycle
+// further on; callers that only need a good iterate (the refinement phases)
+// take it, info->cycles then counts it.
 hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_params &p, int64_t spc,
-                hipStream_t stream, DevScratch &S, hj_info *info)
+                hipStream_t stream, DevScratch &S, hj_info *info, bool latest)
 {
     void *bufs[3] = {xu, xs, (char *)xs + xbytes};
     double *part[2] = {S.partials, S.partials + S.npart / 2};
@@ -252,6 +256,7 @@ hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_para
             if ((r = read_ctrl(S, stream, c)) != HJ_OK) return r;
         }
         final_c = c.status != hj::ST_RUNNING ? c.done_cycle : maxc;
+        if (latest && c.status == hj::ST_CONVERGED) final_c = std::min<int64_t>(c.done_cycle + 1, maxc);
     }
     if (final_c % 3 != 0) {
         HJ_HIP(st.copy(xu, bufs[final_c % 3]));
@@ -344,7 +349,7 @@ hj::GeomVC make_geom_vc(const hj_vc_problem &pr, const hj_params &p)
 }
 
 hj_status drive(const struct Step &st, void *xu, void *xs, size_t xbytes, const hj_params &p, int64_t spc,
-                hipStream_t stream, DevScratch &S, hj_info *info);
+                hipStream_t stream, DevScratch &S, hj_info *info, bool latest = false);
 
 hj_status solve_vc_locked(const hj_vc_problem &pr, const double *f, double *u, const hj_params &P,
                           hipStream_t st, DevScratch &S, hj_info *infos)
@@ -722,7 +727,7 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
     // FP64 residual of x into r32; returns ||f - A x||^2
     auto fp64_residual = [&](double &rsq) -> hj_status {
         HJ_HIP(hj::launch_ctrl_init(S.ctrl, st));
-        HJ_HIP(hj::launch_resid2d_f64_to_f32(g, f, x, r32, S.partials, st));
+        HJ_HIP(hj::launch_resid2d_f64_to_f32(g, f, x, r32, e32, S.partials, st));
         HJ_HIP(hj::launch_judge(S.partials, (int)nbm, S.ctrl, 0, -1.0, st));
         hj::Ctrl c{};
         hj_status rr = read_ctrl(S, st, c);
@@ -753,7 +758,7 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
         hj_params P64 = P;
         P64.rel_tol = std::max(sw, p->rel_tol);
         hj_info i64{};
-        const hj_status s1 = drive(s64, x, S.xbuf, b64, P64, hier ? P.s : 1, st, S, &i64);
+        const hj_status s1 = drive(s64, x, S.xbuf, b64, P64, hier ? P.s : 1, st, S, &i64, true);
         if (s1 != HJ_OK && s1 != HJ_ERR_NOT_CONVERGED) return s1;
         fp64_cycles = i64.cycles;
         r0_phase1 = i64.r0_norm;
@@ -770,11 +775,10 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
     int64_t outer = 0, inner_cycles = 0;
     hj_status status = HJ_OK;
     while (std::isfinite(rk_norm) && rel > p->rel_tol && outer < p->max_outer) {
-        HJ_HIP(hj::launch_fill_f32(g, e32, st));
         hj_params Pk = P;
         Pk.rel_tol = std::max(P.rel_tol, 0.5 * p->rel_tol * r0_norm / rk_norm);
         hj_info ii{};
-        const hj_status si = drive(step, e32, S.xbuf, b32, Pk, hier ? P.s : 1, st, S, &ii);
+        const hj_status si = drive(step, e32, S.xbuf, b32, Pk, hier ? P.s : 1, st, S, &ii, true);
         if (si != HJ_OK && si != HJ_ERR_NOT_CONVERGED) return si;
         inner_cycles += ii.cycles;
         HJ_HIP(hj::launch_axpy_f32_to_f64(g, e32, x, st));

@@ -124,6 +124,7 @@ __global__ __launch_bounds__(256) void k_batch_init(Ctrl *ctrl, int nprob, BCtl 
          p += (int)(gridDim.x * blockDim.x)) {
         Ctrl k{};
         k.done_cycle = -1;
+        k.stop_at = INT64_MAX;
         k.status = ST_RUNNING;
         ctrl[p] = k;
     }

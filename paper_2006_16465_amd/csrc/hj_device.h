@@ -16,6 +16,7 @@ struct Ctrl {
     double last_rsq;     // ||r_c||^2 of the latest judged iterate
     int64_t iter;        // one past the latest judged iterate
     int64_t done_cycle;  // first c that met the tolerance (or went non-finite); -1 otherwise
+    int64_t stop_at;     // cycle kernels evaluating iterate k >= stop_at return at once
     int32_t status;      // 0 running, 1 converged, 2 non-finite, 3 stopped at max_cycles
     int32_t pad;
 };
@@ -108,8 +109,19 @@ __device__ inline void judge(Ctrl *ctrl, int64_t c, double rsq, double tol)
     else if (rel <= tol) st = ST_CONVERGED;
     if (st != ST_RUNNING) {
         ctrl->done_cycle = c;
+        // workgroups of the judging kernel (it evaluates iterate c + 1) that
+        // start after the verdict return at once, as do all later kernels
+        __hip_atomic_store(&ctrl->stop_at, c + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&ctrl->status, st, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// Early exit of a cycle kernel that evaluates iterate k.  After a verdict on
+// iterate c, iterate c + 1 is whole (the kernel that wrote it judged c - 1,
+// which did not stop the solve); iterate c + 2 may be partial.
+__device__ inline bool stopped(const Ctrl *ctrl, int64_t k)
+{
+    return k >= __hip_atomic_load(&ctrl->stop_at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline int32_t read_status(const Ctrl *ctrl)

@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kNT) void k_cycle2d(Geom2 g, const T *__restrict__ 
 {
     static_assert(kNT % TX == 0 && (TX * TY) % kNT == 0, "tile/threads mismatch");
     if (RES) {
-        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (stopped(red.ctrl, red.c)) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(64 * W) void k_cycle2d_reg(Geom2 g, const T *__rest
 {
     constexpr int NT = 64 * W;
     if (RES) {
-        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (stopped(red.ctrl, red.c)) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<NT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kNT) void k_sweep2d(Geom2 g, const T *__restrict__ 
                                                  Red red, double tol)
 {
     if (SWEEP && RES) {
-        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (stopped(red.ctrl, red.c)) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(kNT) void k_cycle1d(Geom1 g, const T *__restrict__ 
                                                  int s, Red red, double tol)
 {
     if (RES) {
-        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (stopped(red.ctrl, red.c)) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kNT) void k_sweep1d(Geom1 g, const T *__restrict__ 
                                                  Red red, double tol)
 {
     if (SWEEP && RES) {
-        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (stopped(red.ctrl, red.c)) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
@@ -250,6 +250,7 @@ __global__ void k_ctrl_init(Ctrl *ctrl)
     ctrl->last_rsq = 0.0;
     ctrl->iter = 0;
     ctrl->done_cycle = -1;
+    ctrl->stop_at = INT64_MAX;
     ctrl->status = ST_RUNNING;
     ctrl->pad = 0;
 }

@@ -136,8 +136,7 @@ hipError_t launch_batch_finalize(int dt, const BProb *probs, int nprob, const Ct
 
 int64_t resid2d_mixed_blocks(const Geom2 &g);
 hipError_t launch_resid2d_f64_to_f32(const Geom2 &g, const double *f, const double *x, float *r32,
-                                     double *part, hipStream_t st);
+                                     float *e32, double *part, hipStream_t st);
 hipError_t launch_axpy_f32_to_f64(const Geom2 &g, const float *e, double *x, hipStream_t st);
-hipError_t launch_fill_f32(const Geom2 &g, float *e, hipStream_t st);
 
 }  // namespace hj

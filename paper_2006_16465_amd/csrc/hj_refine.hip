@@ -1,5 +1,6 @@
 // hj_refine.hip -- kernels of the mixed-precision solve: FP64 residual written
-// in FP32, FP64 correction accumulation, FP32 fill.  The FP32 hierarchical
+// in FP32 (which also clears the FP32 correction), FP64 correction
+// accumulation.  The FP32 hierarchical
 // cycles in between are the ordinary cycle kernels (hj_kernels.hip).
 //
 // Iterative refinement: r = f - A x in FP64; A e = r solved approximately by
@@ -16,10 +17,12 @@ namespace {
 
 constexpr int kBX = 64, kBY = 4, kRPT = 8;  // same column walk as the sweep kernel
 
-// r32 = (float)(f - A x) with x, f in FP64; partial sums of ||f - A x||^2 (FP64).
+// r32 = (float)(f - A x) with x, f in FP64; partial sums of ||f - A x||^2 (FP64);
+// e32 = 0, the start of the next correction solve.
 __global__ __launch_bounds__(256) void k_resid2d_f64_to_f32(Geom2 g, const double *__restrict__ f,
                                                             const double *__restrict__ x,
                                                             float *__restrict__ r32,
+                                                            float *__restrict__ e32,
                                                             double *__restrict__ part)
 {
     const int gx = (g.nx + kBX - 1) / kBX;
@@ -42,6 +45,7 @@ __global__ __launch_bounds__(256) void k_resid2d_f64_to_f32(Geom2 g, const doubl
                 const double e = c + 1 < g.nx ? x[a + 1] : 0.0;
                 const double rr = f[a] - (g.wx * ((2.0 * cen - w) - e) + g.wy * ((2.0 * cen - up) - dn));
                 r32[a] = (float)rr;
+                e32[a] = 0.0f;
                 rsq += rr * rr;
                 up = cen;
                 cen = dn;
@@ -65,16 +69,6 @@ __global__ __launch_bounds__(256) void k_axpy_f32_to_f64(int nx, int ny, int64_t
     }
 }
 
-__global__ __launch_bounds__(256) void k_fill_f32(int nx, int ny, int64_t ld, float *__restrict__ e)
-{
-    const int64_t total = (int64_t)nx * ny;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * 256) {
-        const int64_t r = i / nx, c = i - r * nx;
-        e[r * ld + c] = 0.0f;
-    }
-}
-
 unsigned stride_blocks(int nx, int ny)
 {
     const int64_t total = (int64_t)nx * ny;
@@ -92,9 +86,9 @@ int64_t resid2d_mixed_blocks(const Geom2 &g)
 }
 
 hipError_t launch_resid2d_f64_to_f32(const Geom2 &g, const double *f, const double *x, float *r32,
-                                     double *part, hipStream_t st)
+                                     float *e32, double *part, hipStream_t st)
 {
-    k_resid2d_f64_to_f32<<<(unsigned)resid2d_mixed_blocks(g), 256, 0, st>>>(g, f, x, r32, part);
+    k_resid2d_f64_to_f32<<<(unsigned)resid2d_mixed_blocks(g), 256, 0, st>>>(g, f, x, r32, e32, part);
     return hipGetLastError();
 }
 
@@ -104,10 +98,5 @@ hipError_t launch_axpy_f32_to_f64(const Geom2 &g, const float *e, double *x, hip
     return hipGetLastError();
 }
 
-hipError_t launch_fill_f32(const Geom2 &g, float *e, hipStream_t st)
-{
-    k_fill_f32<<<stride_blocks(g.nx, g.ny), 256, 0, st>>>(g.nx, g.ny, g.ld, e);
-    return hipGetLastError();
-}
 
 }  // namespace hj

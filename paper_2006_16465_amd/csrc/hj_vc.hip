@@ -46,7 +46,7 @@ __global__ __launch_bounds__(kNT) void k_cycle2d_vc(GeomVC g, const double *__re
 {
     static_assert(kNT % TX == 0 && (TX * TY) % kNT == 0, "tile/threads mismatch");
     if (RES) {
-        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (stopped(red.ctrl, red.c)) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kNT) void k_sweep2d_vc(GeomVC g, const double *__re
                                                     double *__restrict__ xout, Red red, double tol)
 {
     if (SWEEP && RES) {
-        if (read_status(red.ctrl) != ST_RUNNING) return;
+        if (stopped(red.ctrl, red.c)) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }

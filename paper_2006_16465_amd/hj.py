@@ -261,7 +261,7 @@ def solve_2d(f, x, h=None, *, hx=None, hy=None, tile=(32, 32), s=16, method="hie
 
 
 def solve_2d_refined(f, x, h=None, *, hx=None, hy=None, tile=(64, 32), s=8, overlap=(14, 14),
-                     method="hierarchical", rel_tol=1e-10, inner_tol=1e-4, switch_tol=0.0,
+                     method="hierarchical", rel_tol=1e-10, inner_tol=1e-6, switch_tol=0.0,
                      inner_max_cycles=100_000, max_outer=50, check_every=0,
                      allow_not_converged=False) -> RefineInfo:
     """FP64 solve: FP64 cycles down to switch_tol (0 = 1e4 * rel_tol), then FP32
