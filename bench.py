@@ -121,6 +121,7 @@ def main():
     ap.add_argument("--batch-tol", type=float, default=1e-8)
     ap.add_argument("--no-diffusion", action="store_true",
                     help="skip the variable-coefficient / adjoint rows")
+    ap.add_argument("--no-1d", action="store_true", help="skip the 1D rows")
     ap.add_argument("--inner-tol", type=float, default=1e-6)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample budget")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -251,6 +252,8 @@ def main():
         extra["batched"] = batched_rows(args, torch, hj, stream)
     if not args.no_diffusion:
         extra["differentiable"] = diffusion_rows(torch, hj, stream)
+    if not args.no_1d:
+        extra["poisson1d"] = rows_1d(torch, hj, stream)
 
     cpu = None
     if not args.no_cpu:
@@ -411,6 +414,39 @@ def batched_rows(args, torch, hj, stream):
                    "converged_one_call_per_problem": conv_s, "problems": len(infos),
                    "cycles_median_converged": float(np.median(cyc)), "cycles_max_converged": int(cyc.max())},
     }
+
+
+def rows_1d(torch, hj, stream):
+    """1D Poisson, N = 256 interior points, 8 random sine modes (seeds 0-4),
+    x0 = 0, to 1e-6: the paper's setting (32-point tiles, s = 16, no overlap),
+    64-point tiles with s = 8 and overlap 14 (a cycle = 8 classical sweeps),
+    and global-memory Jacobi.  Mean ms per problem (median of 5 repeats)."""
+    from paper_2006_16465_amd import workloads as W
+    n = 256
+    h = W.grid_h(n)
+    fs = [torch.from_numpy(W.rhs_1d_modes(n, 8, sd)).cuda() for sd in range(5)]
+    x = torch.zeros_like(fs[0])
+    out = {"workload": "poisson1d_n256: -u'' = f, N = 256, f = 8 random sine modes (seeds 0-4), x0 = 0, to 1e-6"}
+    for name, kw in (("paper_t32_s16", dict(tile=32, s=16, overlap=0)),
+                     ("overlap_t64_s8_o14", dict(tile=64, s=8, overlap=14)),
+                     ("global", dict(method="global"))):
+        ms, cyc = [], []
+        for f in fs:
+            reps = []
+            for _ in range(5):
+                x.zero_()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                info = hj.solve_1d(f, x, h, rel_tol=1e-6, **kw)
+                e1.record(stream)
+                e1.synchronize()
+                reps.append(e0.elapsed_time(e1))
+            ms.append(float(np.median(reps)))
+            cyc.append(info.cycles)
+        out[name] = {"ms_per_problem": round(float(np.mean(ms)), 3), "cycles_per_seed": cyc}
+    log(f"1d: {out}")
+    return out
 
 
 def diffusion_rows(torch, hj, stream):

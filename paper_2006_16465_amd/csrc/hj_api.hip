@@ -185,7 +185,7 @@ hj_status read_ctrl(DevScratch &S, hipStream_t stream, hj::Ctrl &c)
 // further on; callers that only need a good iterate (the refinement phases)
 // take it, info->cycles then counts it.
 hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_params &p, int64_t spc,
-                hipStream_t stream, DevScratch &S, hj_info *info, bool latest)
+                hipStream_t stream, DevScratch &S, hj_info *info, bool latest = false)
 {
     void *bufs[3] = {xu, xs, (char *)xs + xbytes};
     double *part[2] = {S.partials, S.partials + S.npart / 2};
@@ -347,9 +347,6 @@ hj::GeomVC make_geom_vc(const hj_vc_problem &pr, const hj_params &p)
     g.ihy2 = 1.0 / (pr.hy * pr.hy);
     return g;
 }
-
-hj_status drive(const struct Step &st, void *xu, void *xs, size_t xbytes, const hj_params &p, int64_t spc,
-                hipStream_t stream, DevScratch &S, hj_info *info, bool latest = false);
 
 hj_status solve_vc_locked(const hj_vc_problem &pr, const double *f, double *u, const hj_params &P,
                           hipStream_t st, DevScratch &S, hj_info *infos)
