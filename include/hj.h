@@ -202,6 +202,7 @@ typedef struct hj_problem {
 } hj_problem;
 
 #define HJ_BATCH_AUTOTUNE 0x1
+#define HJ_BATCH_REFINE 0x2
 
 typedef struct hj_batch_params {
     hj_params p2;         /* 2D cycle: tile_x in {32, 64}, tile_y in {16, 32, 64, 128},
@@ -212,9 +213,13 @@ typedef struct hj_batch_params {
     int64_t max_cycles;   /* >= 1 */
     int32_t dtype;        /* hj_dtype of every f and x */
     int32_t graph_cycles; /* cycles per graph replay, 0 = 8, at most 1024 */
-    int32_t flags;        /* 0 or HJ_BATCH_AUTOTUNE: choose p2 and p1 with hj_autotune
-                             (2D on the largest 2D problem, tiles limited to the smallest) */
-    int32_t pad;
+    int32_t flags;        /* HJ_BATCH_AUTOTUNE: choose p2 and p1 with hj_autotune (2D on the
+                             largest 2D problem, tiles limited to the smallest);
+                             HJ_BATCH_REFINE: FP64 problems (dtype HJ_F64, rel_tol > 0) solved
+                             as hj_solve_2d_refined does: FP64 cycles down to
+                             min(1, 1e4 * rel_tol), then refinement steps of FP32 correction
+                             cycles, each problem stopping at its own rel_tol */
+    int32_t max_outer;    /* HJ_BATCH_REFINE: refinement steps allowed (0 = 8) */
 } hj_batch_params;
 
 /* Scratch: one iterate array per problem (the sum of the problems' sizes),

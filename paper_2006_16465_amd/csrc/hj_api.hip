@@ -409,7 +409,27 @@ struct BatchScratch {
     hj::BCtl *bc = nullptr;
 };
 
-BatchScratch g_bat[kMaxDev];
+BatchScratch g_bat[kMaxDev];    // FP64 / FP32 batches and phase 1 of refined ones
+BatchScratch g_bat32[kMaxDev];  // FP32 correction solves of refined batches
+
+// Refinement-step scratch of refined batches: FP32 residual and correction
+// arrays, the step tables and the per-problem norms.
+struct RefScratch {
+    char *arena = nullptr;
+    int64_t arena_bytes = 0;
+    hj::BRef *refs = nullptr;
+    int64_t nrefs = 0;
+    int32_t *owner = nullptr;
+    int64_t nowner = 0;
+    double *part = nullptr;
+    int64_t npart = 0;
+    double *rsq = nullptr;
+    int64_t nrsq = 0;
+    double *host = nullptr;  // pinned copy of rsq
+    int64_t nhost = 0;
+};
+
+RefScratch g_ref[kMaxDev];
 
 template <typename T>
 hj_status grow_dev(T *&ptr, int64_t &have, int64_t need)
@@ -585,6 +605,334 @@ hj_status check_problem(const hj_problem &q, hj_dtype dt, int dev, int64_t i)
         if ((r = check_device_ptr(q.f, dev, (at + "f").c_str())) != HJ_OK) return r;
         if ((r = check_device_ptr(q.x, dev, (at + "x").c_str())) != HJ_OK) return r;
     }
+    return HJ_OK;
+}
+
+// One batched solve of validated, device-resident problems with per-problem
+// tolerances (<= 0: fixed count), on the scratch set B.  On return B.host[i]
+// holds problem i's control block and each x its stopping iterate.  Device
+// and lock held by the caller.
+hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, hj_dtype dt,
+                    const hj_params &P2, const hj_params &P1, int64_t max_cycles, int K, hipStream_t st,
+                    DevScratch &S, BatchScratch &B)
+{
+    const int idt = dt == HJ_F64 ? hj::F64 : hj::F32;
+    const size_t es = esize(dt);
+    hj_status r;
+
+    // host tables: problem records and arena offsets
+    std::vector<hj::BProb> hp((size_t)nprob);
+    int64_t arena = 0, npart = 0;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const hj_problem &q = probs[i];
+        hj::BProb &b = hp[(size_t)i];
+        std::memset(&b, 0, sizeof(b));
+        b.dim = q.dim;
+        b.f = q.f;
+        b.x = q.x;
+        int64_t elems = 0;
+        if (q.dim == 2) {
+            b.g2 = make_geom2(q.nx, q.ny, q.ld, q.hx, q.hy, P2);
+            b.nitems = (int64_t)b.g2.ntx * b.g2.nty;
+            elems = q.ny * q.ld;
+        } else {
+            b.g1 = make_geom1(q.nx, q.hx, &P1);
+            b.nitems = hj::cycle1d_blocks(b.g1);
+            elems = q.nx;
+        }
+        b.part0 = npart;
+        b.tol = tols[i];
+        npart += b.nitems;
+        b.s1 = (void *)(intptr_t)arena;  // offset; rebased below
+        arena += ((int64_t)elems * (int64_t)es + 255) / 256 * 256;
+    }
+    if (npart > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "batch too large");
+
+    if (!B.cap) HJ_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
+    if (!B.bc) HJ_HIP(hipMalloc((void **)&B.bc, sizeof(hj::BCtl)));
+    if (!S.ev[0]) {
+        if ((r = scratch_ensure(S, 0, 0)) != HJ_OK) return r;
+    }
+    {
+        char *a8 = (char *)B.arena;
+        int64_t have = B.arena_bytes;
+        if ((r = grow_dev(a8, have, arena)) != HJ_OK) return r;
+        B.arena = a8;
+        B.arena_bytes = have;
+    }
+    if ((r = grow_dev(B.probs, B.nprobs, nprob)) != HJ_OK) return r;
+    if ((r = grow_dev(B.owner, B.nowner, std::max<int64_t>(npart, 1))) != HJ_OK) return r;
+    if ((r = grow_dev(B.part, B.npart, 2 * npart)) != HJ_OK) return r;
+    if ((r = grow_dev(B.ctrl, B.nctrl, nprob)) != HJ_OK) return r;
+    if (nprob > B.nhost) {
+        if (B.host) HJ_HIP(hipHostFree(B.host));
+        B.host = nullptr;
+        B.nhost = 0;
+        HJ_HIP(hipHostMalloc((void **)&B.host, (size_t)(2 * nprob) * sizeof(hj::Ctrl), hipHostMallocDefault));
+        B.nhost = nprob;
+    }
+    for (auto &b : hp) b.s1 = (char *)B.arena + (intptr_t)b.s1;
+    HJ_HIP(hj::launch_batch_init(B.ctrl, (int)nprob, B.bc, max_cycles, st));
+
+    // Work lists of the problems still running (iso 2D, other 2D, 1D, in that
+    // order in one owner array; a problem's items stay contiguous), uploaded
+    // with the updated problem records, and a fixed run of K cycles captured
+    // on them.  Rebuilt when the running problems hold under half of the
+    // listed items, so the tail of long-running problems does not pay for
+    // launching everyone else's finished tiles.  The caller's stream is idle
+    // whenever this runs.
+    std::vector<int32_t> own;
+    int64_t n_iso = 0, n_gen = 0, n_1d = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    };
+    auto rebuild = [&](const hj::Ctrl *snap) -> hj_status {
+        own.clear();
+        for (int pass = 0; pass < 3; ++pass) {
+            const int64_t start = (int64_t)own.size();
+            for (int64_t i = 0; i < nprob; ++i) {
+                hj::BProb &b = hp[(size_t)i];
+                const int kind = b.dim == 1 ? 2 : (b.g2.iso ? 0 : 1);
+                if (kind != pass || (snap && snap[i].status != hj::ST_RUNNING)) continue;
+                b.item0 = (int64_t)own.size() - start;
+                own.insert(own.end(), (size_t)b.nitems, (int32_t)i);
+            }
+            (pass == 0 ? n_iso : pass == 1 ? n_gen : n_1d) = (int64_t)own.size() - start;
+        }
+        HJ_HIP(hipMemcpyAsync(B.probs, hp.data(), hp.size() * sizeof(hj::BProb), hipMemcpyHostToDevice, st));
+        if (!own.empty())
+            HJ_HIP(hipMemcpyAsync(B.owner, own.data(), own.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HJ_HIP(hipStreamSynchronize(st));  // the host tables change on the next rebuild
+        cleanup();
+        const hj::BatchLaunch Li{B.probs, B.owner, n_iso, B.bc, B.ctrl, B.part, npart, P2.s};
+        const hj::BatchLaunch Lg{B.probs, B.owner + n_iso, n_gen, B.bc, B.ctrl, B.part, npart, P2.s};
+        const hj::BatchLaunch L1{B.probs, B.owner + n_iso + n_gen, n_1d, B.bc, B.ctrl, B.part, npart, P1.s};
+        HJ_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int k = 0; k < K && ce == hipSuccess; ++k) {
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, true, Li, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, false, Lg, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle1d(idt, P1.tile_x, L1, B.cap);
+            if (ce == hipSuccess)
+                ce = hj::launch_batch_judge(B.probs, (int)nprob, B.bc, B.ctrl, B.part, npart, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_advance(B.bc, B.cap);
+        }
+        const hipError_t ee = hipStreamEndCapture(B.cap, &graph);
+        if (ce != hipSuccess) {
+            cleanup();
+            return hip_fail(ce, "capturing the batch cycle");
+        }
+        HJ_HIP(ee);
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            cleanup();
+            return hip_fail(ie, "hipGraphInstantiate");
+        }
+        return HJ_OK;
+    };
+    if ((r = rebuild(nullptr)) != HJ_OK) return r;
+
+    // replay with one replay of lookahead; poll the control blocks in between
+    const int64_t replays = (max_cycles + 1 + K - 1) / K;  // cycles 0 .. max_cycles
+    int64_t launched = 0;
+    auto enqueue = [&](int slot) -> hipError_t {
+        hipError_t e = hipGraphLaunch(exec, st);
+        if (e == hipSuccess) ++launched;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(B.host + (size_t)slot * nprob, B.ctrl, (size_t)nprob * sizeof(hj::Ctrl),
+                               hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(S.ev[slot], st);
+        return e;
+    };
+    hipError_t le = enqueue(0);
+    int slot = 0;
+    while (le == hipSuccess) {
+        const bool more = launched < replays;
+        if (more && (le = enqueue(slot ^ 1)) != hipSuccess) break;
+        if ((le = hipEventSynchronize(S.ev[slot])) != hipSuccess) break;
+        const hj::Ctrl *snap = B.host + (size_t)slot * nprob;
+        int64_t live_items = 0;
+        for (int64_t i = 0; i < nprob; ++i)
+            if (snap[i].status == hj::ST_RUNNING) live_items += hp[(size_t)i].nitems;
+        if (live_items == 0 || !more) break;
+        if (2 * live_items < (int64_t)own.size()) {
+            // drain the lookahead replay, then rebuild from its newer snapshot
+            if ((le = hipEventSynchronize(S.ev[slot ^ 1])) != hipSuccess) break;
+            if ((r = rebuild(B.host + (size_t)(slot ^ 1) * nprob)) != HJ_OK) {
+                cleanup();
+                return r;
+            }
+            if (launched >= replays) break;
+            if ((le = enqueue(0)) != hipSuccess) break;
+            slot = 0;
+            continue;
+        }
+        slot ^= 1;
+    }
+    if (le == hipSuccess) le = hj::launch_batch_finalize(idt, B.probs, (int)nprob, B.ctrl, st);
+    if (le == hipSuccess)
+        le = hipMemcpyAsync(B.host, B.ctrl, (size_t)nprob * sizeof(hj::Ctrl), hipMemcpyDeviceToHost, st);
+    if (le == hipSuccess) le = hipStreamSynchronize(st);
+    cleanup();
+    if (le != hipSuccess) return hip_fail(le, "batch replay");
+    return HJ_OK;
+}
+
+
+// Refined batch (HJ_BATCH_REFINE): phase 1 is run_batch in FP64 down to
+// min(1, 1e4 rel_tol); then each step forms every still-running problem's FP64
+// residual (stored FP32, correction cleared), drops the problems that meet
+// rel_tol, solves the corrections of the others in one FP32 batch (each to
+// max(1e-6, rel_tol ||r_0|| / (2 ||r_k||)), as the single-problem refinement),
+// and accumulates x += e in FP64.
+hj_status refine_batch(const hj_problem *probs, int64_t nprob, const hj_batch_params &p, const hj_params &P2,
+                       const hj_params &P1, hipStream_t st, int dev, DevScratch &S, hj_info *infos)
+{
+    BatchScratch &B = g_bat[dev];
+    BatchScratch &B32 = g_bat32[dev];
+    RefScratch &Q = g_ref[dev];
+    const int K = p.graph_cycles ? p.graph_cycles : 8;
+    const double tol = p.rel_tol;
+    const int max_outer = p.max_outer > 0 ? p.max_outer : 8;
+    hj_status r;
+
+    std::vector<double> tols((size_t)nprob, std::min(1.0, 1e4 * tol));
+    if ((r = run_batch(probs, nprob, tols.data(), HJ_F64, P2, P1, p.max_cycles, K, st, S, B)) != HJ_OK) return r;
+    std::vector<double> r0((size_t)nprob), rel((size_t)nprob, 0.0);
+    std::vector<int64_t> cyc((size_t)nprob);
+    for (int64_t i = 0; i < nprob; ++i) {
+        const hj::Ctrl &c = B.host[i];
+        if (c.status == hj::ST_NONFINITE)
+            return fail(HJ_ERR_NONFINITE, "problem " + std::to_string(i) + ": residual norm became non-finite");
+        r0[(size_t)i] = std::sqrt(c.r0sq);
+        cyc[(size_t)i] = c.done_cycle;
+    }
+
+    // FP32 residual and correction arrays (row pitch nx)
+    std::vector<int64_t> off32((size_t)nprob);
+    int64_t arena = 0, items_all = 0;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const int64_t n = probs[i].dim == 2 ? probs[i].nx * probs[i].ny : probs[i].nx;
+        off32[(size_t)i] = arena;
+        arena += (2 * n * 4 + 255) / 256 * 256;
+        items_all += hj::ref_items(probs[i].dim, probs[i].nx, probs[i].ny);
+    }
+    if ((r = grow_dev(Q.arena, Q.arena_bytes, arena)) != HJ_OK) return r;
+    if ((r = grow_dev(Q.refs, Q.nrefs, nprob)) != HJ_OK) return r;
+    if ((r = grow_dev(Q.owner, Q.nowner, std::max<int64_t>(items_all, 1))) != HJ_OK) return r;
+    if ((r = grow_dev(Q.part, Q.npart, std::max<int64_t>(items_all, 1))) != HJ_OK) return r;
+    if ((r = grow_dev(Q.rsq, Q.nrsq, nprob)) != HJ_OK) return r;
+    if (nprob > Q.nhost) {
+        if (Q.host) HJ_HIP(hipHostFree(Q.host));
+        Q.host = nullptr;
+        Q.nhost = 0;
+        HJ_HIP(hipHostMalloc((void **)&Q.host, (size_t)nprob * sizeof(double), hipHostMallocDefault));
+        Q.nhost = nprob;
+    }
+    auto r32_of = [&](int64_t i) { return (float *)(Q.arena + off32[(size_t)i]); };
+    auto e32_of = [&](int64_t i) {
+        const int64_t n = probs[i].dim == 2 ? probs[i].nx * probs[i].ny : probs[i].nx;
+        return r32_of(i) + n;
+    };
+
+    // step tables over a set of problems; the norm kernel fills rsq in that order
+    std::vector<int64_t> act((size_t)nprob);
+    for (int64_t i = 0; i < nprob; ++i) act[(size_t)i] = i;
+    std::vector<hj::BRef> refs;
+    std::vector<int32_t> own;
+    int64_t nitems = 0;
+    auto upload = [&]() -> hj_status {
+        HJ_HIP(hipStreamSynchronize(st));  // earlier uploads read these host vectors
+        refs.assign(act.size(), hj::BRef{});
+        own.clear();
+        for (size_t j = 0; j < act.size(); ++j) {
+            const hj_problem &q = probs[act[j]];
+            hj::BRef &b = refs[j];
+            b.dim = q.dim;
+            b.nx = (int32_t)q.nx;
+            b.ny = q.dim == 2 ? (int32_t)q.ny : 1;
+            b.ld = q.dim == 2 ? q.ld : q.nx;
+            b.wx = 1.0 / (q.hx * q.hx);
+            b.wy = q.dim == 2 ? 1.0 / (q.hy * q.hy) : 0.0;
+            b.f = (const double *)q.f;
+            b.x = (double *)q.x;
+            b.r32 = r32_of(act[j]);
+            b.e32 = e32_of(act[j]);
+            b.item0 = (int64_t)own.size();
+            b.nitems = hj::ref_items(q.dim, q.nx, q.ny);
+            b.part0 = b.item0;
+            own.insert(own.end(), (size_t)b.nitems, (int32_t)j);
+        }
+        nitems = (int64_t)own.size();
+        HJ_HIP(hipMemcpyAsync(Q.refs, refs.data(), refs.size() * sizeof(hj::BRef), hipMemcpyHostToDevice, st));
+        if (nitems)
+            HJ_HIP(hipMemcpyAsync(Q.owner, own.data(), own.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        return HJ_OK;
+    };
+
+    int64_t outer = 0;
+    for (;;) {
+        if ((r = upload()) != HJ_OK) return r;
+        HJ_HIP(hj::launch_batch_ref_resid(Q.refs, Q.owner, nitems, Q.part, st));
+        HJ_HIP(hj::launch_batch_ref_norm(Q.refs, (int)act.size(), Q.part, Q.rsq, st));
+        HJ_HIP(hipMemcpyAsync(Q.host, Q.rsq, act.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HJ_HIP(hipStreamSynchronize(st));
+        std::vector<int64_t> next;
+        std::vector<double> rk;
+        for (size_t j = 0; j < act.size(); ++j) {
+            const int64_t i = act[j];
+            const double nrm = std::sqrt(Q.host[j]);
+            if (!std::isfinite(nrm))
+                return fail(HJ_ERR_NONFINITE, "problem " + std::to_string(i) + ": residual norm became non-finite");
+            rel[(size_t)i] = r0[(size_t)i] > 0.0 ? nrm / r0[(size_t)i] : 0.0;
+            if (rel[(size_t)i] > tol) {
+                next.push_back(i);
+                rk.push_back(nrm);
+            }
+        }
+        if (next.empty() || outer == max_outer) break;
+
+        // FP32 corrections of the problems still above rel_tol
+        std::vector<hj_problem> q32(next.size());
+        std::vector<double> t32(next.size());
+        for (size_t j = 0; j < next.size(); ++j) {
+            const int64_t i = next[j];
+            q32[j] = probs[i];
+            q32[j].ld = probs[i].nx;
+            q32[j].f = r32_of(i);
+            q32[j].x = e32_of(i);
+            t32[j] = std::max(1e-6, 0.5 * tol * r0[(size_t)i] / rk[j]);
+        }
+        if ((r = run_batch(q32.data(), (int64_t)q32.size(), t32.data(), HJ_F32, P2, P1, p.max_cycles, K, st,
+                           S, B32)) != HJ_OK)
+            return r;
+        for (size_t j = 0; j < next.size(); ++j) cyc[(size_t)next[j]] += B32.host[j].done_cycle;
+        act = next;
+        if ((r = upload()) != HJ_OK) return r;
+        HJ_HIP(hj::launch_batch_ref_axpy(Q.refs, Q.owner, nitems, st));
+        ++outer;
+    }
+    HJ_HIP(hipStreamSynchronize(st));
+
+    int64_t bad = -1;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const int s_dim = probs[i].dim == 2 ? P2.s : P1.s;
+        if (infos) {
+            infos[i].cycles = cyc[(size_t)i];
+            infos[i].sweeps = cyc[(size_t)i] * s_dim;
+            infos[i].r0_norm = r0[(size_t)i];
+            infos[i].rel_residual = rel[(size_t)i];
+        }
+        if (rel[(size_t)i] > tol && bad < 0) bad = i;
+    }
+    if (bad >= 0)
+        return fail(HJ_ERR_NOT_CONVERGED, "problem " + std::to_string(bad) + " did not reach rel_tol in " +
+                                              std::to_string(max_outer) + " refinement steps");
     return HJ_OK;
 }
 
@@ -961,8 +1309,12 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
     if (p->max_cycles < 1) return fail(HJ_ERR_INVALID_ARG, "max_cycles must be >= 1");
     if (p->graph_cycles < 0 || p->graph_cycles > 1024)
         return fail(HJ_ERR_INVALID_ARG, "graph_cycles must be in [0, 1024]");
-    if (p->flags & ~HJ_BATCH_AUTOTUNE) return fail(HJ_ERR_INVALID_ARG, "unknown bits in flags");
+    if (p->flags & ~(HJ_BATCH_AUTOTUNE | HJ_BATCH_REFINE)) return fail(HJ_ERR_INVALID_ARG, "unknown bits in flags");
     const bool tune = (p->flags & HJ_BATCH_AUTOTUNE) != 0;
+    const bool refine = (p->flags & HJ_BATCH_REFINE) != 0;
+    if (refine && dt != HJ_F64) return fail(HJ_ERR_INVALID_ARG, "refined batches take FP64 problems");
+    if (refine && !(p->rel_tol > 0.0)) return fail(HJ_ERR_INVALID_ARG, "refined batches need rel_tol > 0");
+    if (p->max_outer < 0) return fail(HJ_ERR_INVALID_ARG, "max_outer must be >= 0");
     hj_status r;
     int64_t n2 = 0, n1 = 0, min_nx = INT64_MAX, min_ny = INT64_MAX;
     for (int64_t i = 0; i < nprob; ++i) {
@@ -1004,171 +1356,13 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
     hipStream_t st = (hipStream_t)stream;
     hj_params P2 = p->p2, P1 = p->p1;
     if (tune && (r = tune_batch_locked(probs, nprob, dt, st, dev, S, P2, P1)) != HJ_OK) return r;
-    const int idt = dt == HJ_F64 ? hj::F64 : hj::F32;
-    const size_t es = esize(dt);
-
-    // host tables: problem records and arena offsets
-    std::vector<hj::BProb> hp((size_t)nprob);
-    int64_t arena = 0, npart = 0;
-    for (int64_t i = 0; i < nprob; ++i) {
-        const hj_problem &q = probs[i];
-        hj::BProb &b = hp[(size_t)i];
-        std::memset(&b, 0, sizeof(b));
-        b.dim = q.dim;
-        b.f = q.f;
-        b.x = q.x;
-        int64_t elems = 0;
-        if (q.dim == 2) {
-            b.g2 = make_geom2(q.nx, q.ny, q.ld, q.hx, q.hy, P2);
-            b.nitems = (int64_t)b.g2.ntx * b.g2.nty;
-            elems = q.ny * q.ld;
-        } else {
-            b.g1 = make_geom1(q.nx, q.hx, &P1);
-            b.nitems = hj::cycle1d_blocks(b.g1);
-            elems = q.nx;
-        }
-        b.part0 = npart;
-        npart += b.nitems;
-        b.s1 = (void *)(intptr_t)arena;  // offset; rebased below
-        arena += ((int64_t)elems * (int64_t)es + 255) / 256 * 256;
-    }
-    if (npart > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "batch too large");
-
+    if (refine) return refine_batch(probs, nprob, *p, P2, P1, st, dev, S, infos);
     BatchScratch &B = g_bat[dev];
-    if (!B.cap) HJ_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
-    if (!B.bc) HJ_HIP(hipMalloc((void **)&B.bc, sizeof(hj::BCtl)));
-    if (!S.ev[0]) {
-        if ((r = scratch_ensure(S, 0, 0)) != HJ_OK) return r;
-    }
-    {
-        char *a8 = (char *)B.arena;
-        int64_t have = B.arena_bytes;
-        if ((r = grow_dev(a8, have, arena)) != HJ_OK) return r;
-        B.arena = a8;
-        B.arena_bytes = have;
-    }
-    if ((r = grow_dev(B.probs, B.nprobs, nprob)) != HJ_OK) return r;
-    if ((r = grow_dev(B.owner, B.nowner, std::max<int64_t>(npart, 1))) != HJ_OK) return r;
-    if ((r = grow_dev(B.part, B.npart, 2 * npart)) != HJ_OK) return r;
-    if ((r = grow_dev(B.ctrl, B.nctrl, nprob)) != HJ_OK) return r;
-    if (nprob > B.nhost) {
-        if (B.host) HJ_HIP(hipHostFree(B.host));
-        B.host = nullptr;
-        B.nhost = 0;
-        HJ_HIP(hipHostMalloc((void **)&B.host, (size_t)(2 * nprob) * sizeof(hj::Ctrl), hipHostMallocDefault));
-        B.nhost = nprob;
-    }
-    for (auto &b : hp) b.s1 = (char *)B.arena + (intptr_t)b.s1;
+    std::vector<double> tols((size_t)nprob, p->rel_tol > 0.0 ? p->rel_tol : -1.0);
+    if ((r = run_batch(probs, nprob, tols.data(), dt, P2, P1, p->max_cycles,
+                       p->graph_cycles ? p->graph_cycles : 8, st, S, B)) != HJ_OK)
+        return r;
     const double tol = p->rel_tol > 0.0 ? p->rel_tol : -1.0;
-    HJ_HIP(hj::launch_batch_init(B.ctrl, (int)nprob, B.bc, p->max_cycles, tol, st));
-
-    // Work lists of the problems still running (iso 2D, other 2D, 1D, in that
-    // order in one owner array; a problem's items stay contiguous), uploaded
-    // with the updated problem records, and a fixed run of K cycles captured
-    // on them.  Rebuilt when the running problems hold under half of the
-    // listed items, so the tail of long-running problems does not pay for
-    // launching everyone else's finished tiles.  The caller's stream is idle
-    // whenever this runs.
-    const int K = p->graph_cycles ? p->graph_cycles : 8;
-    std::vector<int32_t> own;
-    int64_t n_iso = 0, n_gen = 0, n_1d = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    auto cleanup = [&]() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
-    };
-    auto rebuild = [&](const hj::Ctrl *snap) -> hj_status {
-        own.clear();
-        for (int pass = 0; pass < 3; ++pass) {
-            const int64_t start = (int64_t)own.size();
-            for (int64_t i = 0; i < nprob; ++i) {
-                hj::BProb &b = hp[(size_t)i];
-                const int kind = b.dim == 1 ? 2 : (b.g2.iso ? 0 : 1);
-                if (kind != pass || (snap && snap[i].status != hj::ST_RUNNING)) continue;
-                b.item0 = (int64_t)own.size() - start;
-                own.insert(own.end(), (size_t)b.nitems, (int32_t)i);
-            }
-            (pass == 0 ? n_iso : pass == 1 ? n_gen : n_1d) = (int64_t)own.size() - start;
-        }
-        HJ_HIP(hipMemcpyAsync(B.probs, hp.data(), hp.size() * sizeof(hj::BProb), hipMemcpyHostToDevice, st));
-        if (!own.empty())
-            HJ_HIP(hipMemcpyAsync(B.owner, own.data(), own.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        HJ_HIP(hipStreamSynchronize(st));  // the host tables change on the next rebuild
-        cleanup();
-        const hj::BatchLaunch Li{B.probs, B.owner, n_iso, B.bc, B.ctrl, B.part, npart, P2.s};
-        const hj::BatchLaunch Lg{B.probs, B.owner + n_iso, n_gen, B.bc, B.ctrl, B.part, npart, P2.s};
-        const hj::BatchLaunch L1{B.probs, B.owner + n_iso + n_gen, n_1d, B.bc, B.ctrl, B.part, npart, P1.s};
-        HJ_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
-        hipError_t ce = hipSuccess;
-        for (int k = 0; k < K && ce == hipSuccess; ++k) {
-            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, true, Li, B.cap);
-            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, false, Lg, B.cap);
-            if (ce == hipSuccess) ce = hj::launch_batch_cycle1d(idt, P1.tile_x, L1, B.cap);
-            if (ce == hipSuccess)
-                ce = hj::launch_batch_judge(B.probs, (int)nprob, B.bc, B.ctrl, B.part, npart, B.cap);
-            if (ce == hipSuccess) ce = hj::launch_batch_advance(B.bc, B.cap);
-        }
-        const hipError_t ee = hipStreamEndCapture(B.cap, &graph);
-        if (ce != hipSuccess) {
-            cleanup();
-            return hip_fail(ce, "capturing the batch cycle");
-        }
-        HJ_HIP(ee);
-        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (ie != hipSuccess) {
-            cleanup();
-            return hip_fail(ie, "hipGraphInstantiate");
-        }
-        return HJ_OK;
-    };
-    if ((r = rebuild(nullptr)) != HJ_OK) return r;
-
-    // replay with one replay of lookahead; poll the control blocks in between
-    const int64_t replays = (p->max_cycles + 1 + K - 1) / K;  // cycles 0 .. max_cycles
-    int64_t launched = 0;
-    auto enqueue = [&](int slot) -> hipError_t {
-        hipError_t e = hipGraphLaunch(exec, st);
-        if (e == hipSuccess) ++launched;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(B.host + (size_t)slot * nprob, B.ctrl, (size_t)nprob * sizeof(hj::Ctrl),
-                               hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipEventRecord(S.ev[slot], st);
-        return e;
-    };
-    hipError_t le = enqueue(0);
-    int slot = 0;
-    while (le == hipSuccess) {
-        const bool more = launched < replays;
-        if (more && (le = enqueue(slot ^ 1)) != hipSuccess) break;
-        if ((le = hipEventSynchronize(S.ev[slot])) != hipSuccess) break;
-        const hj::Ctrl *snap = B.host + (size_t)slot * nprob;
-        int64_t live_items = 0;
-        for (int64_t i = 0; i < nprob; ++i)
-            if (snap[i].status == hj::ST_RUNNING) live_items += hp[(size_t)i].nitems;
-        if (live_items == 0 || !more) break;
-        if (2 * live_items < (int64_t)own.size()) {
-            // drain the lookahead replay, then rebuild from its newer snapshot
-            if ((le = hipEventSynchronize(S.ev[slot ^ 1])) != hipSuccess) break;
-            if ((r = rebuild(B.host + (size_t)(slot ^ 1) * nprob)) != HJ_OK) {
-                cleanup();
-                return r;
-            }
-            if (launched >= replays) break;
-            if ((le = enqueue(0)) != hipSuccess) break;
-            slot = 0;
-            continue;
-        }
-        slot ^= 1;
-    }
-    if (le == hipSuccess) le = hj::launch_batch_finalize(idt, B.probs, (int)nprob, B.ctrl, st);
-    if (le == hipSuccess)
-        le = hipMemcpyAsync(B.host, B.ctrl, (size_t)nprob * sizeof(hj::Ctrl), hipMemcpyDeviceToHost, st);
-    if (le == hipSuccess) le = hipStreamSynchronize(st);
-    cleanup();
-    if (le != hipSuccess) return hip_fail(le, "batch replay");
 
     hj_status status = HJ_OK;
     int64_t bad = -1;

@@ -85,8 +85,8 @@ __global__ __launch_bounds__(kNT) void k_batch_cycle1d(const BProb *__restrict__
 }
 
 // One wavefront per problem: partials of iterate c summed lane-strided in
-// index order, then a fixed butterfly; lane 0 judges.  With tol <= 0 no
-// problem converges and every one stops at max_cycles.
+// index order, then a fixed butterfly; lane 0 judges against the problem's
+// own tolerance.  With tol <= 0 it never converges and stops at max_cycles.
 __global__ __launch_bounds__(256) void k_batch_judge(const BProb *__restrict__ probs, int nprob,
                                                      const BCtl *bc, Ctrl *ctrl,
                                                      const double *part, int64_t npart)
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_batch_judge(const BProb *__restrict__ p
     acc = wave_sum(acc);
     if (lane == 0) {
         Ctrl *k = &ctrl[p];
-        judge(k, c, acc, bc->tol);
+        judge(k, c, acc, probs[p].tol);
         if (k->status == ST_RUNNING && c >= bc->max_cycles) {
             k->done_cycle = c;
             __hip_atomic_store(&k->status, (int32_t)ST_LIMIT, __ATOMIC_RELAXED,
@@ -118,7 +118,7 @@ __global__ void k_batch_advance(BCtl *bc)
 }
 
 __global__ __launch_bounds__(256) void k_batch_init(Ctrl *ctrl, int nprob, BCtl *bc,
-                                                    int64_t max_cycles, double tol)
+                                                    int64_t max_cycles)
 {
     for (int p = (int)(blockIdx.x * blockDim.x + threadIdx.x); p < nprob;
          p += (int)(gridDim.x * blockDim.x)) {
@@ -131,7 +131,6 @@ __global__ __launch_bounds__(256) void k_batch_init(Ctrl *ctrl, int nprob, BCtl 
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         bc->cycle = 0;
         bc->max_cycles = max_cycles;
-        bc->tol = tol;
     }
 }
 
@@ -200,7 +199,143 @@ hipError_t bcyc1_t(int t, const BatchLaunch &L, hipStream_t st)
     }
 }
 
+// ---------------------------------------------------------------- refinement
+constexpr int kRBX = 64, kRRPT = 8;  // 2D blocks: 64 columns x (4 x 8) rows
+constexpr int kR1 = 2048;           // 1D block: 256 threads x 8 points
+
+// r = f - A x in FP64 (the oracle's residual association), stored as FP32;
+// the correction starts from zero; this thread's share of ||r||^2.
+__device__ double ref_resid_block(const BRef &P, int64_t blk)
+{
+    double rsq = 0.0;
+    if (P.dim == 2) {
+        const int gx = (P.nx + kRBX - 1) / kRBX;
+        const int by = (int)(blk / gx), bx = (int)(blk - (int64_t)by * gx);
+        const int c = bx * kRBX + (int)(threadIdx.x % kRBX);
+        const int rbeg = (by * 4 + (int)(threadIdx.x / kRBX)) * kRRPT;
+        if (c < P.nx && rbeg < P.ny) {
+            const int64_t ld = P.ld;
+            const double *x = P.x;
+            double up = rbeg > 0 ? x[(int64_t)(rbeg - 1) * ld + c] : 0.0;
+            double cen = x[(int64_t)rbeg * ld + c];
+            for (int i = 0; i < kRRPT; ++i) {
+                const int r = rbeg + i;
+                if (r >= P.ny) break;
+                const int64_t a = (int64_t)r * ld + c;
+                const double dn = r + 1 < P.ny ? x[a + ld] : 0.0;
+                const double w = c > 0 ? x[a - 1] : 0.0;
+                const double e = c + 1 < P.nx ? x[a + 1] : 0.0;
+                const double rr = res2(P.f[a], cen, w, e, up, dn, P.wx, P.wy);
+                const int64_t a32 = (int64_t)r * P.nx + c;
+                P.r32[a32] = (float)rr;
+                P.e32[a32] = 0.0f;
+                rsq += rr * rr;
+                up = cen;
+                cen = dn;
+            }
+        }
+    } else {
+        const int64_t n = P.nx;
+        const int64_t i0 = blk * kR1 + threadIdx.x;
+        for (int j = 0; j < kR1 / kNT; ++j) {
+            const int64_t i = i0 + (int64_t)j * kNT;
+            if (i >= n) break;
+            const double w = i > 0 ? P.x[i - 1] : 0.0;
+            const double e = i + 1 < n ? P.x[i + 1] : 0.0;
+            const double rr = res1(P.f[i], P.x[i], w, e, P.wx);
+            P.r32[i] = (float)rr;
+            P.e32[i] = 0.0f;
+            rsq += rr * rr;
+        }
+    }
+    return rsq;
+}
+
+__global__ __launch_bounds__(kNT) void k_batch_ref_resid(const BRef *__restrict__ refs,
+                                                         const int32_t *__restrict__ owner,
+                                                         int64_t nitems, double *part)
+{
+    const int64_t w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= nitems) return;
+    const BRef &P = refs[owner[w]];
+    const int64_t blk = w - P.item0;
+    const double rsq = ref_resid_block(P, blk);
+    post_partial_at<kNT>(rsq, &part[P.part0 + blk]);
+}
+
+__global__ __launch_bounds__(256) void k_batch_ref_norm(const BRef *__restrict__ refs, int nref,
+                                                        const double *part, double *rsq)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const int p = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+    if (p >= nref) return;
+    const double *base = part + refs[p].part0;
+    const int64_t n = refs[p].nitems;
+    double acc = 0.0;
+    for (int64_t i = lane; i < n; i += 64) acc += base[i];
+    acc = wave_sum(acc);
+    if (lane == 0) rsq[p] = acc;
+}
+
+__global__ __launch_bounds__(kNT) void k_batch_ref_axpy(const BRef *__restrict__ refs,
+                                                        const int32_t *__restrict__ owner,
+                                                        int64_t nitems)
+{
+    const int64_t w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= nitems) return;
+    const BRef &P = refs[owner[w]];
+    const int64_t blk = w - P.item0;
+    if (P.dim == 2) {
+        const int gx = (P.nx + kRBX - 1) / kRBX;
+        const int by = (int)(blk / gx), bx = (int)(blk - (int64_t)by * gx);
+        const int c = bx * kRBX + (int)(threadIdx.x % kRBX);
+        const int rbeg = (by * 4 + (int)(threadIdx.x / kRBX)) * kRRPT;
+        if (c >= P.nx) return;
+        for (int i = 0; i < kRRPT; ++i) {
+            const int r = rbeg + i;
+            if (r >= P.ny) break;
+            double *xp = &P.x[(int64_t)r * P.ld + c];
+            *xp = *xp + (double)P.e32[(int64_t)r * P.nx + c];
+        }
+    } else {
+        const int64_t i0 = blk * kR1 + threadIdx.x;
+        for (int j = 0; j < kR1 / kNT; ++j) {
+            const int64_t i = i0 + (int64_t)j * kNT;
+            if (i >= P.nx) break;
+            P.x[i] = P.x[i] + (double)P.e32[i];
+        }
+    }
+}
+
 }  // namespace
+
+int64_t ref_items(int dim, int64_t nx, int64_t ny)
+{
+    if (dim == 2) return ((nx + kRBX - 1) / kRBX) * ((ny + 4 * kRRPT - 1) / (4 * kRRPT));
+    return (nx + kR1 - 1) / kR1;
+}
+
+hipError_t launch_batch_ref_resid(const BRef *refs, const int32_t *owner, int64_t nitems, double *part,
+                                  hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    k_batch_ref_resid<<<(unsigned)nitems, kNT, 0, st>>>(refs, owner, nitems, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ref_norm(const BRef *refs, int nref, const double *part, double *rsq,
+                                 hipStream_t st)
+{
+    k_batch_ref_norm<<<(unsigned)((nref + 3) / 4), 256, 0, st>>>(refs, nref, part, rsq);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_ref_axpy(const BRef *refs, const int32_t *owner, int64_t nitems, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    k_batch_ref_axpy<<<(unsigned)nitems, kNT, 0, st>>>(refs, owner, nitems);
+    return hipGetLastError();
+}
 
 bool batch2d_supported(int tx, int ty)
 {
@@ -236,11 +371,10 @@ hipError_t launch_batch_advance(BCtl *bc, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_init(Ctrl *ctrl, int nprob, BCtl *bc, int64_t max_cycles, double tol,
-                             hipStream_t st)
+hipError_t launch_batch_init(Ctrl *ctrl, int nprob, BCtl *bc, int64_t max_cycles, hipStream_t st)
 {
     const unsigned nb = (unsigned)((nprob + 255) / 256);
-    k_batch_init<<<nb > 0 ? nb : 1, 256, 0, st>>>(ctrl, nprob, bc, max_cycles, tol);
+    k_batch_init<<<nb > 0 ? nb : 1, 256, 0, st>>>(ctrl, nprob, bc, max_cycles);
     return hipGetLastError();
 }
 

@@ -103,12 +103,12 @@ struct BProb {
     int64_t item0;   // first work item of this problem in its dimension's list
     int64_t nitems;  // work items: 2D tiles, or 1D tile groups
     int64_t part0;   // first residual partial slot
+    double tol;      // relative tolerance (<= 0: run max_cycles cycles)
 };
 
 struct BCtl {
     int64_t cycle;       // cycle the next kernels run (advanced on the device)
     int64_t max_cycles;  // problems still running after iterate max_cycles stop
-    double tol;          // relative tolerance (<= 0: run max_cycles cycles)
 };
 
 struct BatchLaunch {
@@ -122,6 +122,34 @@ struct BatchLaunch {
     int s;
 };
 
+// One problem of a batched refinement step: FP64 f, x (pitch ld), FP32
+// residual and correction (pitch nx).  Work items: 2D blocks of 64 columns x
+// 32 rows, 1D blocks of 2048 points.
+struct BRef {
+    int32_t dim;
+    int32_t nx, ny;
+    int32_t pad;
+    int64_t ld;
+    double wx, wy;   // 1 / hx^2, 1 / hy^2 (1D: wx)
+    const double *f;
+    double *x;
+    float *r32;
+    float *e32;
+    int64_t item0;   // first work item of this problem
+    int64_t nitems;
+    int64_t part0;   // first partial slot
+};
+
+int64_t ref_items(int dim, int64_t nx, int64_t ny);
+// r32 = f - A x (FP64, stored FP32), e32 = 0, partials of ||r||^2 per item
+hipError_t launch_batch_ref_resid(const BRef *refs, const int32_t *owner, int64_t nitems, double *part,
+                                  hipStream_t st);
+// rsq[p] = sum of problem p's partials (fixed order)
+hipError_t launch_batch_ref_norm(const BRef *refs, int nref, const double *part, double *rsq,
+                                 hipStream_t st);
+// x += (double) e32 over the listed items
+hipError_t launch_batch_ref_axpy(const BRef *refs, const int32_t *owner, int64_t nitems, hipStream_t st);
+
 bool batch2d_supported(int tx, int ty);
 // iso: the work list holds only problems with hx == hy (else only the others)
 hipError_t launch_batch_cycle2d(int dt, int tx, int ty, bool iso, const BatchLaunch &L, hipStream_t st);
@@ -129,8 +157,7 @@ hipError_t launch_batch_cycle1d(int dt, int t, const BatchLaunch &L, hipStream_t
 hipError_t launch_batch_judge(const BProb *probs, int nprob, const BCtl *bc, Ctrl *ctrl,
                               const double *part, int64_t npart, hipStream_t st);
 hipError_t launch_batch_advance(BCtl *bc, hipStream_t st);
-hipError_t launch_batch_init(Ctrl *ctrl, int nprob, BCtl *bc, int64_t max_cycles, double tol,
-                             hipStream_t st);
+hipError_t launch_batch_init(Ctrl *ctrl, int nprob, BCtl *bc, int64_t max_cycles, hipStream_t st);
 hipError_t launch_batch_finalize(int dt, const BProb *probs, int nprob, const Ctrl *ctrl,
                                  hipStream_t st);
 

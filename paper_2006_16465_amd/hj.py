@@ -79,10 +79,12 @@ class Problem(ctypes.Structure):
 class BatchParams(ctypes.Structure):
     _fields_ = [("p2", Params), ("p1", Params), ("rel_tol", ctypes.c_double),
                 ("max_cycles", ctypes.c_int64), ("dtype", ctypes.c_int32),
-                ("graph_cycles", ctypes.c_int32), ("flags", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("graph_cycles", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("max_outer", ctypes.c_int32)]
 
 
 HJ_BATCH_AUTOTUNE = 0x1
+HJ_BATCH_REFINE = 0x2
 
 
 class _Info(ctypes.Structure):
@@ -341,13 +343,15 @@ def autotune_batch(problems):
 
 def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 18), tile_1d=256,
                   s_1d=16, overlap_1d=30, max_cycles=1_000_000, graph_cycles=8, autotune=False,
-                  allow_not_converged=False) -> list:
+                  refine=False, max_outer=0, allow_not_converged=False) -> list:
     """Solve many independent problems together (hj_solve_batched).
 
     problems: sequence of (f, x, h) or (f, x, hx, hy); f, x GPU tensors of one
     dtype, shape (n,) for 1D and (ny, nx) for 2D (row-major).  Each x is updated
     in place.  2D problems use the cycle (tile, s, overlap), 1D problems
     (tile_1d, s_1d, overlap_1d); autotune=True lets the library choose both.
+    refine=True (FP64 problems): FP64 cycles down to 1e4 * rel_tol, then FP32
+    correction cycles inside FP64 refinement (at most max_outer steps, 0 = 8).
     Returns one Info per problem."""
     import torch
     if not problems:
@@ -360,7 +364,8 @@ def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 1
     bp.max_cycles = max_cycles
     bp.dtype = dt
     bp.graph_cycles = graph_cycles
-    bp.flags = HJ_BATCH_AUTOTUNE if autotune else 0
+    bp.flags = (HJ_BATCH_AUTOTUNE if autotune else 0) | (HJ_BATCH_REFINE if refine else 0)
+    bp.max_outer = max_outer
     infos = (_Info * len(problems))()
     f0 = problems[0][0]
     with _device(f0):

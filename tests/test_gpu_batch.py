@@ -168,3 +168,36 @@ def test_autotuned_batch_converges():
     assert ov == (2 * s - 2, 2 * s - 2) and us > 0
     t1, s1, o1, us1 = hj.autotune(1, 100000)
     assert o1 == 2 * s1 - 2 and us1 > 0
+
+
+def kappa(kind, n):
+    """Condition number of the Dirichlet Laplacian: 1D and 2D square grids of side n."""
+    return 1.0 / np.tan(np.pi / (2 * (n + 1))) ** 2
+
+
+def test_refined_batch_reaches_tolerance_and_matches_fp64_oracle(orc):
+    """FP64 cycles down to 1e4 * tol, then FP32 corrections per problem inside
+    FP64 refinement: every problem meets 1e-10 (FP64 residual formed here),
+    lies within kappa * (r + r_oracle) of the oracle's FP64 solve, and spends
+    about as many cycles as the FP64 solve."""
+    probs = make_batch(6)
+    got, infos = gpu_batch(probs, rel_tol=1e-10, refine=True)
+    for i, pr in enumerate(probs):
+        kind, f, hx, hy = pr
+        r = residual_np(kind, f, got[i], hx, hy if hy else hx)
+        xo, co, relo, _ = oracle_solve(orc, pr, 1e-10)
+        n = max(f.shape)
+        err = np.linalg.norm(got[i] - xo) / np.linalg.norm(xo)
+        say(f"refined batch[{i}] {kind} {f.shape}: rel {r:.2e}, cycles {infos[i].cycles} (FP64 {co}), err {err:.1e}")
+        assert infos[i].status == hj.HJ_OK and r <= 1.001e-10 and infos[i].rel_residual <= 1e-10
+        assert err <= kappa(kind, n) * 2 * (r + relo) + 1e-14
+        assert abs(infos[i].cycles - co) <= 6 + co // 25
+
+
+def test_refined_batch_validates():
+    f = dev(np.ones((64, 64)), torch.float32)
+    with pytest.raises(hj.HJError):
+        hj.solve_batched([(f, torch.zeros_like(f), 0.01)], rel_tol=1e-8, refine=True)  # FP32 problems
+    f64 = dev(np.ones((64, 64)))
+    with pytest.raises(hj.HJError):
+        hj.solve_batched([(f64, torch.zeros_like(f64), 0.01)], rel_tol=0.0, refine=True)
