@@ -399,6 +399,12 @@ def batched_rows(args, torch, hj, stream):
     conv_s = sum(1 for i in infos_s if i.status == hj.HJ_OK)
     log(f"batched: to {tol:g} (cap {C} cycles): batched {tt:.1f} ms ({len(conv)} of {len(infos)} converged), "
         f"one call per problem {tts:.1f} ms ({conv_s})")
+    clear()
+    tr, infos_r = timed(lambda: hj.solve_batched(table, rel_tol=tol, max_cycles=C, refine=True, max_outer=3,
+                                                 allow_not_converged=True, **shape))
+    conv_r = sum(1 for i in infos_r if i.status == hj.HJ_OK)
+    log(f"batched: to {tol:g} with FP32 corrections in FP64 refinement (cap {C} cycles per phase, 3 steps): "
+        f"{tr:.1f} ms ({conv_r} of {len(infos_r)} converged)")
     cyc = np.array([i.cycles for i in conv]) if conv else np.array([0])
     return {
         "workload": "512 square 2D (side log-uniform [64, 1024]) + 128 1D (N log-uniform [1e3, 1e6]) Poisson "
@@ -413,6 +419,9 @@ def batched_rows(args, torch, hj, stream):
                    "one_call_per_problem_ms": round(tts, 2), "converged": len(conv),
                    "converged_one_call_per_problem": conv_s, "problems": len(infos),
                    "cycles_median_converged": float(np.median(cyc)), "cycles_max_converged": int(cyc.max())},
+        "to_tol_refined": {"tol": tol, "method": "FP64 cycles to 1e4 * tol, then FP32 corrections in FP64 "
+                           "refinement (hj_solve_batched, HJ_BATCH_REFINE)", "cycle_cap_per_phase": C,
+                           "max_outer": 3, "ms": round(tr, 2), "converged": conv_r, "problems": len(infos_r)},
     }
 
 

@@ -210,7 +210,8 @@ typedef struct hj_batch_params {
                              nx >= tile_x and ny >= tile_y); method HJ_HIERARCHICAL */
     hj_params p1;         /* 1D cycle: tile_x in 32..1024, overlap_x, s */
     double rel_tol;       /* per problem; <= 0: every problem runs exactly max_cycles cycles */
-    int64_t max_cycles;   /* >= 1 */
+    int64_t max_cycles;   /* >= 1: cycles per problem (HJ_BATCH_REFINE: FP64 and FP32 cycles
+                             of all phases together) */
     int32_t dtype;        /* hj_dtype of every f and x */
     int32_t graph_cycles; /* cycles per graph replay, 0 = 8, at most 1024 */
     int32_t flags;        /* HJ_BATCH_AUTOTUNE: choose p2 and p1 with hj_autotune (2D on the
@@ -228,8 +229,8 @@ typedef struct hj_batch_params {
  * infos[i].rel_residual <= rel_tol (NaN: its residual became non-finite).
  * Problems must not share x arrays.  Returns HJ_OK when every problem met rel_tol
  * (or ran max_cycles in fixed-count mode), HJ_ERR_NOT_CONVERGED if some
- * stopped at max_cycles (their latest iterate is in x), HJ_ERR_NONFINITE if
- * some residual became non-finite. */
+ * stopped at max_cycles or, refined, after max_outer steps (their latest
+ * iterate is in x), HJ_ERR_NONFINITE if some residual became non-finite. */
 hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batch_params *p,
                            void *stream, hj_info *infos);
 

@@ -609,13 +609,15 @@ hj_status check_problem(const hj_problem &q, hj_dtype dt, int dev, int64_t i)
 }
 
 // One batched solve of validated, device-resident problems with per-problem
-// tolerances (<= 0: fixed count), on the scratch set B.  On return B.host[i]
-// holds problem i's control block and each x its stopping iterate.  Device
-// and lock held by the caller.
-hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, hj_dtype dt,
-                    const hj_params &P2, const hj_params &P1, int64_t max_cycles, int K, hipStream_t st,
+// tolerances (<= 0: fixed count) and cycle caps (each >= 1), on the scratch
+// set B.  On return B.host[i] holds problem i's control block and each x its
+// stopping iterate.  Device and lock held by the caller.
+hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, const int64_t *caps,
+                    hj_dtype dt, const hj_params &P2, const hj_params &P1, int K, hipStream_t st,
                     DevScratch &S, BatchScratch &B)
 {
+    int64_t max_cycles = 1;
+    for (int64_t i = 0; i < nprob; ++i) max_cycles = std::max(max_cycles, caps[i]);
     const int idt = dt == HJ_F64 ? hj::F64 : hj::F32;
     const size_t es = esize(dt);
     hj_status r;
@@ -642,6 +644,7 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, 
         }
         b.part0 = npart;
         b.tol = tols[i];
+        b.max_cycles = caps[i];
         npart += b.nitems;
         b.s1 = (void *)(intptr_t)arena;  // offset; rebased below
         arena += ((int64_t)elems * (int64_t)es + 255) / 256 * 256;
@@ -789,7 +792,8 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, 
 // residual (stored FP32, correction cleared), drops the problems that meet
 // rel_tol, solves the corrections of the others in one FP32 batch (each to
 // max(1e-6, rel_tol ||r_0|| / (2 ||r_k||)), as the single-problem refinement),
-// and accumulates x += e in FP64.
+// and accumulates x += e in FP64.  max_cycles caps each problem's cycles over
+// all phases together: an inner solve gets what is left of its budget.
 hj_status refine_batch(const hj_problem *probs, int64_t nprob, const hj_batch_params &p, const hj_params &P2,
                        const hj_params &P1, hipStream_t st, int dev, DevScratch &S, hj_info *infos)
 {
@@ -802,7 +806,8 @@ hj_status refine_batch(const hj_problem *probs, int64_t nprob, const hj_batch_pa
     hj_status r;
 
     std::vector<double> tols((size_t)nprob, std::min(1.0, 1e4 * tol));
-    if ((r = run_batch(probs, nprob, tols.data(), HJ_F64, P2, P1, p.max_cycles, K, st, S, B)) != HJ_OK) return r;
+    std::vector<int64_t> caps((size_t)nprob, p.max_cycles);
+    if ((r = run_batch(probs, nprob, tols.data(), caps.data(), HJ_F64, P2, P1, K, st, S, B)) != HJ_OK) return r;
     std::vector<double> r0((size_t)nprob), rel((size_t)nprob, 0.0);
     std::vector<int64_t> cyc((size_t)nprob);
     for (int64_t i = 0; i < nprob; ++i) {
@@ -890,7 +895,7 @@ hj_status refine_batch(const hj_problem *probs, int64_t nprob, const hj_batch_pa
             if (!std::isfinite(nrm))
                 return fail(HJ_ERR_NONFINITE, "problem " + std::to_string(i) + ": residual norm became non-finite");
             rel[(size_t)i] = r0[(size_t)i] > 0.0 ? nrm / r0[(size_t)i] : 0.0;
-            if (rel[(size_t)i] > tol) {
+            if (rel[(size_t)i] > tol && cyc[(size_t)i] < p.max_cycles) {
                 next.push_back(i);
                 rk.push_back(nrm);
             }
@@ -900,6 +905,7 @@ hj_status refine_batch(const hj_problem *probs, int64_t nprob, const hj_batch_pa
         // FP32 corrections of the problems still above rel_tol
         std::vector<hj_problem> q32(next.size());
         std::vector<double> t32(next.size());
+        std::vector<int64_t> c32(next.size());
         for (size_t j = 0; j < next.size(); ++j) {
             const int64_t i = next[j];
             q32[j] = probs[i];
@@ -907,9 +913,10 @@ hj_status refine_batch(const hj_problem *probs, int64_t nprob, const hj_batch_pa
             q32[j].f = r32_of(i);
             q32[j].x = e32_of(i);
             t32[j] = std::max(1e-6, 0.5 * tol * r0[(size_t)i] / rk[j]);
+            c32[j] = p.max_cycles - cyc[(size_t)i];  // what is left of the problem's budget
         }
-        if ((r = run_batch(q32.data(), (int64_t)q32.size(), t32.data(), HJ_F32, P2, P1, p.max_cycles, K, st,
-                           S, B32)) != HJ_OK)
+        if ((r = run_batch(q32.data(), (int64_t)q32.size(), t32.data(), c32.data(), HJ_F32, P2, P1, K, st, S,
+                           B32)) != HJ_OK)
             return r;
         for (size_t j = 0; j < next.size(); ++j) cyc[(size_t)next[j]] += B32.host[j].done_cycle;
         act = next;
@@ -931,7 +938,8 @@ hj_status refine_batch(const hj_problem *probs, int64_t nprob, const hj_batch_pa
         if (rel[(size_t)i] > tol && bad < 0) bad = i;
     }
     if (bad >= 0)
-        return fail(HJ_ERR_NOT_CONVERGED, "problem " + std::to_string(bad) + " did not reach rel_tol in " +
+        return fail(HJ_ERR_NOT_CONVERGED, "problem " + std::to_string(bad) + " did not reach rel_tol within " +
+                                              std::to_string(p.max_cycles) + " cycles and " +
                                               std::to_string(max_outer) + " refinement steps");
     return HJ_OK;
 }
@@ -1359,7 +1367,8 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
     if (refine) return refine_batch(probs, nprob, *p, P2, P1, st, dev, S, infos);
     BatchScratch &B = g_bat[dev];
     std::vector<double> tols((size_t)nprob, p->rel_tol > 0.0 ? p->rel_tol : -1.0);
-    if ((r = run_batch(probs, nprob, tols.data(), dt, P2, P1, p->max_cycles,
+    std::vector<int64_t> caps((size_t)nprob, p->max_cycles);
+    if ((r = run_batch(probs, nprob, tols.data(), caps.data(), dt, P2, P1,
                        p->graph_cycles ? p->graph_cycles : 8, st, S, B)) != HJ_OK)
         return r;
     const double tol = p->rel_tol > 0.0 ? p->rel_tol : -1.0;

@@ -86,7 +86,8 @@ __global__ __launch_bounds__(kNT) void k_batch_cycle1d(const BProb *__restrict__
 
 // One wavefront per problem: partials of iterate c summed lane-strided in
 // index order, then a fixed butterfly; lane 0 judges against the problem's
-// own tolerance.  With tol <= 0 it never converges and stops at max_cycles.
+// own tolerance.  With tol <= 0 it never converges and stops at its own
+// max_cycles.
 __global__ __launch_bounds__(256) void k_batch_judge(const BProb *__restrict__ probs, int nprob,
                                                      const BCtl *bc, Ctrl *ctrl,
                                                      const double *part, int64_t npart)
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(256) void k_batch_judge(const BProb *__restrict__ p
     if (lane == 0) {
         Ctrl *k = &ctrl[p];
         judge(k, c, acc, probs[p].tol);
-        if (k->status == ST_RUNNING && c >= bc->max_cycles) {
+        if (k->status == ST_RUNNING && c >= probs[p].max_cycles) {
             k->done_cycle = c;
             __hip_atomic_store(&k->status, (int32_t)ST_LIMIT, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);

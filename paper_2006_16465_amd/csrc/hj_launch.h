@@ -104,11 +104,12 @@ struct BProb {
     int64_t nitems;  // work items: 2D tiles, or 1D tile groups
     int64_t part0;   // first residual partial slot
     double tol;      // relative tolerance (<= 0: run max_cycles cycles)
+    int64_t max_cycles;  // this problem stops running after iterate max_cycles
 };
 
 struct BCtl {
     int64_t cycle;       // cycle the next kernels run (advanced on the device)
-    int64_t max_cycles;  // problems still running after iterate max_cycles stop
+    int64_t max_cycles;  // largest per-problem cap (replays run to it)
 };
 
 struct BatchLaunch {

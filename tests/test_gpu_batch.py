@@ -201,3 +201,24 @@ def test_refined_batch_validates():
     f64 = dev(np.ones((64, 64)))
     with pytest.raises(hj.HJError):
         hj.solve_batched([(f64, torch.zeros_like(f64), 0.01)], rel_tol=0.0, refine=True)
+
+
+def test_refined_batch_cycle_cap_covers_all_phases():
+    """With refinement, max_cycles bounds FP64 and FP32 cycles together: no
+    problem spends more, the ones that stop short of rel_tol used all of it,
+    and the reported residual is that of the iterate left in x."""
+    probs = make_batch(6)
+    _, free = gpu_batch(probs, rel_tol=1e-10, refine=True)
+    cap = int(np.median([i.cycles for i in free]))
+    got, infos = gpu_batch(probs, rel_tol=1e-10, refine=True, max_cycles=cap, allow_not_converged=True)
+    assert any(i.status == hj.HJ_ERR_NOT_CONVERGED for i in infos)
+    assert any(i.status == hj.HJ_OK for i in infos)
+    for i, (kind, f, hx, hy) in enumerate(probs):
+        r = residual_np(kind, f, got[i], hx, hy if hy else hx)
+        say(f"capped refined batch[{i}] {kind} {f.shape}: cycles {infos[i].cycles}, rel {r:.2e}")
+        assert 0 < infos[i].cycles <= cap
+        assert abs(infos[i].rel_residual - r) <= 1e-6 * r
+        if infos[i].status == hj.HJ_OK:
+            assert r <= 1.001e-10
+        else:
+            assert infos[i].rel_residual > 1e-10 and infos[i].cycles == cap
