@@ -403,7 +403,7 @@ def batched_rows(args, torch, hj, stream):
     tr, infos_r = timed(lambda: hj.solve_batched(table, rel_tol=tol, max_cycles=C, refine=True, max_outer=3,
                                                  allow_not_converged=True, **shape))
     conv_r = sum(1 for i in infos_r if i.status == hj.HJ_OK)
-    log(f"batched: to {tol:g} with FP32 corrections in FP64 refinement (cap {C} cycles per phase, 3 steps): "
+    log(f"batched: to {tol:g} with FP32 corrections in FP64 refinement (cap {C} cycles per problem, all phases): "
         f"{tr:.1f} ms ({conv_r} of {len(infos_r)} converged)")
     cyc = np.array([i.cycles for i in conv]) if conv else np.array([0])
     return {
@@ -419,9 +419,12 @@ def batched_rows(args, torch, hj, stream):
                    "one_call_per_problem_ms": round(tts, 2), "converged": len(conv),
                    "converged_one_call_per_problem": conv_s, "problems": len(infos),
                    "cycles_median_converged": float(np.median(cyc)), "cycles_max_converged": int(cyc.max())},
-        "to_tol_refined": {"tol": tol, "method": "FP64 cycles to 1e4 * tol, then FP32 corrections in FP64 "
-                           "refinement (hj_solve_batched, HJ_BATCH_REFINE)", "cycle_cap_per_phase": C,
-                           "max_outer": 3, "ms": round(tr, 2), "converged": conv_r, "problems": len(infos_r)},
+        "to_tol_refined": {"tol": tol, "method": "per problem: FP64 cycles down to min(1e4 tol, tol / 8F) "
+                           "(F its predicted FP32 floor), then FP32 corrections inside FP64 refinement "
+                           "(hj_solve_batched, HJ_BATCH_REFINE)", "cycle_cap": C,
+                           "max_outer": 3, "ms": round(tr, 2), "converged": conv_r, "problems": len(infos_r),
+                           "cycles_sum": int(sum(i.cycles for i in infos_r)),
+                           "cycles_sum_fp64": int(sum(i.cycles for i in infos))},
     }
 
 

@@ -402,34 +402,13 @@ struct BatchScratch {
     int64_t nowner = 0;
     double *part = nullptr;
     int64_t npart = 0;
-    hj::Ctrl *ctrl = nullptr;
-    int64_t nctrl = 0;
-    hj::Ctrl *host = nullptr;  // 2 x nhost pinned
-    int64_t nhost = 0;
-    hj::BCtl *bc = nullptr;
-};
-
-BatchScratch g_bat[kMaxDev];    // FP64 / FP32 batches and phase 1 of refined ones
-BatchScratch g_bat32[kMaxDev];  // FP32 correction solves of refined batches
-
-// Refinement-step scratch of refined batches: FP32 residual and correction
-// arrays, the step tables and the per-problem norms.
-struct RefScratch {
-    char *arena = nullptr;
-    int64_t arena_bytes = 0;
-    hj::BRef *refs = nullptr;
-    int64_t nrefs = 0;
-    int32_t *owner = nullptr;
-    int64_t nowner = 0;
-    double *part = nullptr;
-    int64_t npart = 0;
-    double *rsq = nullptr;
-    int64_t nrsq = 0;
-    double *host = nullptr;  // pinned copy of rsq
+    hj::BState *state = nullptr;
+    int64_t nstate = 0;
+    hj::BState *host = nullptr;  // 2 x nhost pinned
     int64_t nhost = 0;
 };
 
-RefScratch g_ref[kMaxDev];
+BatchScratch g_bat[kMaxDev];
 
 template <typename T>
 hj_status grow_dev(T *&ptr, int64_t &have, int64_t need)
@@ -608,51 +587,62 @@ hj_status check_problem(const hj_problem &q, hj_dtype dt, int dev, int64_t i)
     return HJ_OK;
 }
 
-// One batched solve of validated, device-resident problems with per-problem
-// tolerances (<= 0: fixed count) and cycle caps (each >= 1), on the scratch
-// set B.  On return B.host[i] holds problem i's control block and each x its
-// stopping iterate.  Device and lock held by the caller.
-hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, const int64_t *caps,
-                    hj_dtype dt, const hj_params &P2, const hj_params &P1, int K, hipStream_t st,
+// One batched solve of validated, device-resident problems on the scratch
+// set B: plain (rf.refine = 0: cycles of precision dt on each problem) or
+// refined (FP64 problems; FP32 corrections inside FP64 refinement, each
+// problem on its own schedule).  On return B.host[i] holds problem i's state
+// and each x its result.  Device and lock held by the caller.
+hj_status run_batch(const hj_problem *probs, int64_t nprob, hj_dtype dt, double tol, int64_t max_cycles,
+                    const hj::BRefine &rf, const hj_params &P2, const hj_params &P1, int K, hipStream_t st,
                     DevScratch &S, BatchScratch &B)
 {
-    int64_t max_cycles = 1;
-    for (int64_t i = 0; i < nprob; ++i) max_cycles = std::max(max_cycles, caps[i]);
     const int idt = dt == HJ_F64 ? hj::F64 : hj::F32;
     const size_t es = esize(dt);
+    const bool refine = rf.refine != 0;
     hj_status r;
 
-    // host tables: problem records and arena offsets
+    // host tables: problem records, arena offsets (scratch x; refined: FP32
+    // residual and two correction buffers, all with the pitch of x)
+    auto align = [](int64_t b) { return (b + 255) / 256 * 256; };
     std::vector<hj::BProb> hp((size_t)nprob);
+    std::vector<int64_t> off((size_t)nprob * 4, 0);
     int64_t arena = 0, npart = 0;
     for (int64_t i = 0; i < nprob; ++i) {
         const hj_problem &q = probs[i];
         hj::BProb &b = hp[(size_t)i];
         std::memset(&b, 0, sizeof(b));
         b.dim = q.dim;
+        b.dt = idt;
         b.f = q.f;
         b.x = q.x;
         int64_t elems = 0;
         if (q.dim == 2) {
             b.g2 = make_geom2(q.nx, q.ny, q.ld, q.hx, q.hy, P2);
             b.nitems = (int64_t)b.g2.ntx * b.g2.nty;
+            b.s = P2.s;
             elems = q.ny * q.ld;
         } else {
             b.g1 = make_geom1(q.nx, q.hx, &P1);
             b.nitems = hj::cycle1d_blocks(b.g1);
+            b.s = P1.s;
             elems = q.nx;
         }
         b.part0 = npart;
-        b.tol = tols[i];
-        b.max_cycles = caps[i];
         npart += b.nitems;
-        b.s1 = (void *)(intptr_t)arena;  // offset; rebased below
-        arena += ((int64_t)elems * (int64_t)es + 255) / 256 * 256;
+        b.rnitems = refine ? hj::ref_items(q.dim, q.nx, q.ny) : 0;
+        b.tol = tol;
+        b.max_cycles = max_cycles;
+        off[(size_t)i * 4] = arena;
+        arena += align(elems * (int64_t)es);
+        if (refine)
+            for (int k = 1; k < 4; ++k) {
+                off[(size_t)i * 4 + k] = arena;
+                arena += align(elems * 4);
+            }
     }
     if (npart > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "batch too large");
 
     if (!B.cap) HJ_HIP(hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
-    if (!B.bc) HJ_HIP(hipMalloc((void **)&B.bc, sizeof(hj::BCtl)));
     if (!S.ev[0]) {
         if ((r = scratch_ensure(S, 0, 0)) != HJ_OK) return r;
     }
@@ -665,25 +655,34 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, 
     }
     if ((r = grow_dev(B.probs, B.nprobs, nprob)) != HJ_OK) return r;
     if ((r = grow_dev(B.owner, B.nowner, std::max<int64_t>(npart, 1))) != HJ_OK) return r;
-    if ((r = grow_dev(B.part, B.npart, 2 * npart)) != HJ_OK) return r;
-    if ((r = grow_dev(B.ctrl, B.nctrl, nprob)) != HJ_OK) return r;
+    if ((r = grow_dev(B.part, B.npart, std::max<int64_t>(npart, 1))) != HJ_OK) return r;
+    if ((r = grow_dev(B.state, B.nstate, nprob)) != HJ_OK) return r;
     if (nprob > B.nhost) {
         if (B.host) HJ_HIP(hipHostFree(B.host));
         B.host = nullptr;
         B.nhost = 0;
-        HJ_HIP(hipHostMalloc((void **)&B.host, (size_t)(2 * nprob) * sizeof(hj::Ctrl), hipHostMallocDefault));
+        HJ_HIP(hipHostMalloc((void **)&B.host, (size_t)(2 * nprob) * sizeof(hj::BState), hipHostMallocDefault));
         B.nhost = nprob;
     }
-    for (auto &b : hp) b.s1 = (char *)B.arena + (intptr_t)b.s1;
-    HJ_HIP(hj::launch_batch_init(B.ctrl, (int)nprob, B.bc, max_cycles, st));
+    char *base = (char *)B.arena;
+    for (int64_t i = 0; i < nprob; ++i) {
+        hj::BProb &b = hp[(size_t)i];
+        b.s1 = base + off[(size_t)i * 4];
+        if (refine) {
+            b.r32 = (float *)(base + off[(size_t)i * 4 + 1]);
+            b.e0 = (float *)(base + off[(size_t)i * 4 + 2]);
+            b.e1 = (float *)(base + off[(size_t)i * 4 + 3]);
+        }
+    }
+    HJ_HIP(hj::launch_batch_init(B.state, (int)nprob, st));
 
-    // Work lists of the problems still running (iso 2D, other 2D, 1D, in that
-    // order in one owner array; a problem's items stay contiguous), uploaded
-    // with the updated problem records, and a fixed run of K cycles captured
-    // on them.  Rebuilt when the running problems hold under half of the
-    // listed items, so the tail of long-running problems does not pay for
-    // launching everyone else's finished tiles.  The caller's stream is idle
-    // whenever this runs.
+    // Work lists of the problems still running (iso 2D, other 2D, 1D, in
+    // that order in one owner array; a problem's items stay contiguous),
+    // uploaded with the updated problem records, and a fixed run of K steps
+    // captured on them.  Rebuilt when the running
+    // problems hold under half of the listed items, so the tail of
+    // long-running problems does not pay for launching everyone else's
+    // finished tiles.  The caller's stream is idle whenever this runs.
     std::vector<int32_t> own;
     int64_t n_iso = 0, n_gen = 0, n_1d = 0;
     hipGraph_t graph = nullptr;
@@ -694,7 +693,7 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, 
         exec = nullptr;
         graph = nullptr;
     };
-    auto rebuild = [&](const hj::Ctrl *snap) -> hj_status {
+    auto rebuild = [&](const hj::BState *snap) -> hj_status {
         own.clear();
         for (int pass = 0; pass < 3; ++pass) {
             const int64_t start = (int64_t)own.size();
@@ -712,18 +711,16 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, 
             HJ_HIP(hipMemcpyAsync(B.owner, own.data(), own.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
         HJ_HIP(hipStreamSynchronize(st));  // the host tables change on the next rebuild
         cleanup();
-        const hj::BatchLaunch Li{B.probs, B.owner, n_iso, B.bc, B.ctrl, B.part, npart, P2.s};
-        const hj::BatchLaunch Lg{B.probs, B.owner + n_iso, n_gen, B.bc, B.ctrl, B.part, npart, P2.s};
-        const hj::BatchLaunch L1{B.probs, B.owner + n_iso + n_gen, n_1d, B.bc, B.ctrl, B.part, npart, P1.s};
+        const hj::BatchLaunch Li{B.probs, B.owner, n_iso, B.state, B.part, P2.s};
+        const hj::BatchLaunch Lg{B.probs, B.owner + n_iso, n_gen, B.state, B.part, P2.s};
+        const hj::BatchLaunch L1{B.probs, B.owner + n_iso + n_gen, n_1d, B.state, B.part, P1.s};
         HJ_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
         for (int k = 0; k < K && ce == hipSuccess; ++k) {
-            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, true, Li, B.cap);
-            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, P2.tile_x, P2.tile_y, false, Lg, B.cap);
-            if (ce == hipSuccess) ce = hj::launch_batch_cycle1d(idt, P1.tile_x, L1, B.cap);
-            if (ce == hipSuccess)
-                ce = hj::launch_batch_judge(B.probs, (int)nprob, B.bc, B.ctrl, B.part, npart, B.cap);
-            if (ce == hipSuccess) ce = hj::launch_batch_advance(B.bc, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, refine, P2.tile_x, P2.tile_y, true, Li, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, refine, P2.tile_x, P2.tile_y, false, Lg, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle1d(idt, refine, P1.tile_x, L1, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_judge(B.probs, (int)nprob, B.state, B.part, rf, B.cap);
         }
         const hipError_t ee = hipStreamEndCapture(B.cap, &graph);
         if (ce != hipSuccess) {
@@ -740,25 +737,29 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, 
     };
     if ((r = rebuild(nullptr)) != HJ_OK) return r;
 
-    // replay with one replay of lookahead; poll the control blocks in between
-    const int64_t replays = (max_cycles + 1 + K - 1) / K;  // cycles 0 .. max_cycles
+    // Steps: a plain problem stops by its judge of iterate max_cycles; a
+    // refined one within max_cycles counted cycles plus, per correction
+    // solve, a refinement step and at most one cycle that no result counts.
+    const int64_t steps = refine ? max_cycles + 3 * (int64_t)rf.max_outer + 8 : max_cycles + 1;
+    const int64_t replays = (steps + K - 1) / K;
     int64_t launched = 0;
     auto enqueue = [&](int slot) -> hipError_t {
         hipError_t e = hipGraphLaunch(exec, st);
         if (e == hipSuccess) ++launched;
         if (e == hipSuccess)
-            e = hipMemcpyAsync(B.host + (size_t)slot * nprob, B.ctrl, (size_t)nprob * sizeof(hj::Ctrl),
+            e = hipMemcpyAsync(B.host + (size_t)slot * nprob, B.state, (size_t)nprob * sizeof(hj::BState),
                                hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipEventRecord(S.ev[slot], st);
         return e;
     };
+    // replay with one replay of lookahead; poll the states in between
     hipError_t le = enqueue(0);
     int slot = 0;
     while (le == hipSuccess) {
         const bool more = launched < replays;
         if (more && (le = enqueue(slot ^ 1)) != hipSuccess) break;
         if ((le = hipEventSynchronize(S.ev[slot])) != hipSuccess) break;
-        const hj::Ctrl *snap = B.host + (size_t)slot * nprob;
+        const hj::BState *snap = B.host + (size_t)slot * nprob;
         int64_t live_items = 0;
         for (int64_t i = 0; i < nprob; ++i)
             if (snap[i].status == hj::ST_RUNNING) live_items += hp[(size_t)i].nitems;
@@ -777,170 +778,12 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, const double *tols, 
         }
         slot ^= 1;
     }
-    if (le == hipSuccess) le = hj::launch_batch_finalize(idt, B.probs, (int)nprob, B.ctrl, st);
+    if (le == hipSuccess) le = hj::launch_batch_finalize(B.probs, (int)nprob, B.state, st);
     if (le == hipSuccess)
-        le = hipMemcpyAsync(B.host, B.ctrl, (size_t)nprob * sizeof(hj::Ctrl), hipMemcpyDeviceToHost, st);
+        le = hipMemcpyAsync(B.host, B.state, (size_t)nprob * sizeof(hj::BState), hipMemcpyDeviceToHost, st);
     if (le == hipSuccess) le = hipStreamSynchronize(st);
     cleanup();
     if (le != hipSuccess) return hip_fail(le, "batch replay");
-    return HJ_OK;
-}
-
-
-// Refined batch (HJ_BATCH_REFINE): phase 1 is run_batch in FP64 down to
-// min(1, 1e4 rel_tol); then each step forms every still-running problem's FP64
-// residual (stored FP32, correction cleared), drops the problems that meet
-// rel_tol, solves the corrections of the others in one FP32 batch (each to
-// max(1e-6, rel_tol ||r_0|| / (2 ||r_k||)), as the single-problem refinement),
-// and accumulates x += e in FP64.  max_cycles caps each problem's cycles over
-// all phases together: an inner solve gets what is left of its budget.
-hj_status refine_batch(const hj_problem *probs, int64_t nprob, const hj_batch_params &p, const hj_params &P2,
-                       const hj_params &P1, hipStream_t st, int dev, DevScratch &S, hj_info *infos)
-{
-    BatchScratch &B = g_bat[dev];
-    BatchScratch &B32 = g_bat32[dev];
-    RefScratch &Q = g_ref[dev];
-    const int K = p.graph_cycles ? p.graph_cycles : 8;
-    const double tol = p.rel_tol;
-    const int max_outer = p.max_outer > 0 ? p.max_outer : 8;
-    hj_status r;
-
-    std::vector<double> tols((size_t)nprob, std::min(1.0, 1e4 * tol));
-    std::vector<int64_t> caps((size_t)nprob, p.max_cycles);
-    if ((r = run_batch(probs, nprob, tols.data(), caps.data(), HJ_F64, P2, P1, K, st, S, B)) != HJ_OK) return r;
-    std::vector<double> r0((size_t)nprob), rel((size_t)nprob, 0.0);
-    std::vector<int64_t> cyc((size_t)nprob);
-    for (int64_t i = 0; i < nprob; ++i) {
-        const hj::Ctrl &c = B.host[i];
-        if (c.status == hj::ST_NONFINITE)
-            return fail(HJ_ERR_NONFINITE, "problem " + std::to_string(i) + ": residual norm became non-finite");
-        r0[(size_t)i] = std::sqrt(c.r0sq);
-        cyc[(size_t)i] = c.done_cycle;
-    }
-
-    // FP32 residual and correction arrays (row pitch nx)
-    std::vector<int64_t> off32((size_t)nprob);
-    int64_t arena = 0, items_all = 0;
-    for (int64_t i = 0; i < nprob; ++i) {
-        const int64_t n = probs[i].dim == 2 ? probs[i].nx * probs[i].ny : probs[i].nx;
-        off32[(size_t)i] = arena;
-        arena += (2 * n * 4 + 255) / 256 * 256;
-        items_all += hj::ref_items(probs[i].dim, probs[i].nx, probs[i].ny);
-    }
-    if ((r = grow_dev(Q.arena, Q.arena_bytes, arena)) != HJ_OK) return r;
-    if ((r = grow_dev(Q.refs, Q.nrefs, nprob)) != HJ_OK) return r;
-    if ((r = grow_dev(Q.owner, Q.nowner, std::max<int64_t>(items_all, 1))) != HJ_OK) return r;
-    if ((r = grow_dev(Q.part, Q.npart, std::max<int64_t>(items_all, 1))) != HJ_OK) return r;
-    if ((r = grow_dev(Q.rsq, Q.nrsq, nprob)) != HJ_OK) return r;
-    if (nprob > Q.nhost) {
-        if (Q.host) HJ_HIP(hipHostFree(Q.host));
-        Q.host = nullptr;
-        Q.nhost = 0;
-        HJ_HIP(hipHostMalloc((void **)&Q.host, (size_t)nprob * sizeof(double), hipHostMallocDefault));
-        Q.nhost = nprob;
-    }
-    auto r32_of = [&](int64_t i) { return (float *)(Q.arena + off32[(size_t)i]); };
-    auto e32_of = [&](int64_t i) {
-        const int64_t n = probs[i].dim == 2 ? probs[i].nx * probs[i].ny : probs[i].nx;
-        return r32_of(i) + n;
-    };
-
-    // step tables over a set of problems; the norm kernel fills rsq in that order
-    std::vector<int64_t> act((size_t)nprob);
-    for (int64_t i = 0; i < nprob; ++i) act[(size_t)i] = i;
-    std::vector<hj::BRef> refs;
-    std::vector<int32_t> own;
-    int64_t nitems = 0;
-    auto upload = [&]() -> hj_status {
-        HJ_HIP(hipStreamSynchronize(st));  // earlier uploads read these host vectors
-        refs.assign(act.size(), hj::BRef{});
-        own.clear();
-        for (size_t j = 0; j < act.size(); ++j) {
-            const hj_problem &q = probs[act[j]];
-            hj::BRef &b = refs[j];
-            b.dim = q.dim;
-            b.nx = (int32_t)q.nx;
-            b.ny = q.dim == 2 ? (int32_t)q.ny : 1;
-            b.ld = q.dim == 2 ? q.ld : q.nx;
-            b.wx = 1.0 / (q.hx * q.hx);
-            b.wy = q.dim == 2 ? 1.0 / (q.hy * q.hy) : 0.0;
-            b.f = (const double *)q.f;
-            b.x = (double *)q.x;
-            b.r32 = r32_of(act[j]);
-            b.e32 = e32_of(act[j]);
-            b.item0 = (int64_t)own.size();
-            b.nitems = hj::ref_items(q.dim, q.nx, q.ny);
-            b.part0 = b.item0;
-            own.insert(own.end(), (size_t)b.nitems, (int32_t)j);
-        }
-        nitems = (int64_t)own.size();
-        HJ_HIP(hipMemcpyAsync(Q.refs, refs.data(), refs.size() * sizeof(hj::BRef), hipMemcpyHostToDevice, st));
-        if (nitems)
-            HJ_HIP(hipMemcpyAsync(Q.owner, own.data(), own.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        return HJ_OK;
-    };
-
-    int64_t outer = 0;
-    for (;;) {
-        if ((r = upload()) != HJ_OK) return r;
-        HJ_HIP(hj::launch_batch_ref_resid(Q.refs, Q.owner, nitems, Q.part, st));
-        HJ_HIP(hj::launch_batch_ref_norm(Q.refs, (int)act.size(), Q.part, Q.rsq, st));
-        HJ_HIP(hipMemcpyAsync(Q.host, Q.rsq, act.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        HJ_HIP(hipStreamSynchronize(st));
-        std::vector<int64_t> next;
-        std::vector<double> rk;
-        for (size_t j = 0; j < act.size(); ++j) {
-            const int64_t i = act[j];
-            const double nrm = std::sqrt(Q.host[j]);
-            if (!std::isfinite(nrm))
-                return fail(HJ_ERR_NONFINITE, "problem " + std::to_string(i) + ": residual norm became non-finite");
-            rel[(size_t)i] = r0[(size_t)i] > 0.0 ? nrm / r0[(size_t)i] : 0.0;
-            if (rel[(size_t)i] > tol && cyc[(size_t)i] < p.max_cycles) {
-                next.push_back(i);
-                rk.push_back(nrm);
-            }
-        }
-        if (next.empty() || outer == max_outer) break;
-
-        // FP32 corrections of the problems still above rel_tol
-        std::vector<hj_problem> q32(next.size());
-        std::vector<double> t32(next.size());
-        std::vector<int64_t> c32(next.size());
-        for (size_t j = 0; j < next.size(); ++j) {
-            const int64_t i = next[j];
-            q32[j] = probs[i];
-            q32[j].ld = probs[i].nx;
-            q32[j].f = r32_of(i);
-            q32[j].x = e32_of(i);
-            t32[j] = std::max(1e-6, 0.5 * tol * r0[(size_t)i] / rk[j]);
-            c32[j] = p.max_cycles - cyc[(size_t)i];  // what is left of the problem's budget
-        }
-        if ((r = run_batch(q32.data(), (int64_t)q32.size(), t32.data(), c32.data(), HJ_F32, P2, P1, K, st, S,
-                           B32)) != HJ_OK)
-            return r;
-        for (size_t j = 0; j < next.size(); ++j) cyc[(size_t)next[j]] += B32.host[j].done_cycle;
-        act = next;
-        if ((r = upload()) != HJ_OK) return r;
-        HJ_HIP(hj::launch_batch_ref_axpy(Q.refs, Q.owner, nitems, st));
-        ++outer;
-    }
-    HJ_HIP(hipStreamSynchronize(st));
-
-    int64_t bad = -1;
-    for (int64_t i = 0; i < nprob; ++i) {
-        const int s_dim = probs[i].dim == 2 ? P2.s : P1.s;
-        if (infos) {
-            infos[i].cycles = cyc[(size_t)i];
-            infos[i].sweeps = cyc[(size_t)i] * s_dim;
-            infos[i].r0_norm = r0[(size_t)i];
-            infos[i].rel_residual = rel[(size_t)i];
-        }
-        if (rel[(size_t)i] > tol && bad < 0) bad = i;
-    }
-    if (bad >= 0)
-        return fail(HJ_ERR_NOT_CONVERGED, "problem " + std::to_string(bad) + " did not reach rel_tol within " +
-                                              std::to_string(p.max_cycles) + " cycles and " +
-                                              std::to_string(max_outer) + " refinement steps");
     return HJ_OK;
 }
 
@@ -1364,26 +1207,31 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
     hipStream_t st = (hipStream_t)stream;
     hj_params P2 = p->p2, P1 = p->p1;
     if (tune && (r = tune_batch_locked(probs, nprob, dt, st, dev, S, P2, P1)) != HJ_OK) return r;
-    if (refine) return refine_batch(probs, nprob, *p, P2, P1, st, dev, S, infos);
     BatchScratch &B = g_bat[dev];
-    std::vector<double> tols((size_t)nprob, p->rel_tol > 0.0 ? p->rel_tol : -1.0);
-    std::vector<int64_t> caps((size_t)nprob, p->max_cycles);
-    if ((r = run_batch(probs, nprob, tols.data(), caps.data(), dt, P2, P1,
-                       p->graph_cycles ? p->graph_cycles : 8, st, S, B)) != HJ_OK)
-        return r;
     const double tol = p->rel_tol > 0.0 ? p->rel_tol : -1.0;
+    hj::BRefine rf{};
+    if (refine) {
+        rf.refine = 1;
+        rf.max_outer = p->max_outer > 0 ? p->max_outer : 8;
+        rf.switch_tol = std::min(1.0, 1e4 * tol);
+        rf.inner_min = 1e-6;
+        rf.fmax = 1.0 / 80.0;  // FP32 then takes at least one decade (tol / 8F >= 10 tol)
+    }
+    if ((r = run_batch(probs, nprob, dt, tol, p->max_cycles, rf, P2, P1, p->graph_cycles ? p->graph_cycles : 8,
+                       st, S, B)) != HJ_OK)
+        return r;
 
     hj_status status = HJ_OK;
     int64_t bad = -1;
     for (int64_t i = 0; i < nprob; ++i) {
-        const hj::Ctrl &c = B.host[i];
+        const hj::BState &c = B.host[i];
         const int s_dim = probs[i].dim == 2 ? P2.s : P1.s;
         if (infos) {
-            infos[i].cycles = c.done_cycle;
-            infos[i].sweeps = c.done_cycle * s_dim;
+            infos[i].cycles = c.used;
+            infos[i].sweeps = c.used * s_dim;
             infos[i].r0_norm = std::sqrt(c.r0sq);
-            infos[i].rel_residual = c.r0sq > 0.0 ? std::sqrt(c.last_rsq) / std::sqrt(c.r0sq) : 0.0;
-            if (!std::isfinite(c.last_rsq)) infos[i].rel_residual = NAN;
+            infos[i].rel_residual = c.r0sq > 0.0 ? std::sqrt(c.rsq) / std::sqrt(c.r0sq) : 0.0;
+            if (!std::isfinite(c.rsq)) infos[i].rel_residual = NAN;
         }
         if (c.status == hj::ST_NONFINITE) {
             status = HJ_ERR_NONFINITE;
@@ -1396,7 +1244,7 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
     if (status == HJ_ERR_NONFINITE)
         return fail(status, "problem " + std::to_string(bad) + ": residual norm became non-finite");
     if (status == HJ_ERR_NOT_CONVERGED)
-        return fail(status, "problem " + std::to_string(bad) + " reached max_cycles before rel_tol");
+        return fail(status, "problem " + std::to_string(bad) + " did not reach rel_tol within max_cycles");
     return HJ_OK;
 }
 

@@ -88,80 +88,94 @@ hipError_t launch_resid_vc(const GeomVC &g, const double *f, const double *x, do
 hipError_t launch_grad_a_vc(const GeomVC &g, const double *u, const double *lam, int nb,
                             int64_t bstride, double *grad, int64_t ldg, hipStream_t st);
 
-// mixed precision helpers (hj_refine.hip)
 // ---------------------------------------------------------------- batches
-// One problem of a batch on the device.  Buffer 0 is the caller's x, buffer 1
-// a scratch array of the same layout; iterate c lives in buffer c & 1.
+// One problem of a batch on the device.  Main buffers: 0 is the caller's x,
+// 1 a scratch array of the same layout.  A refined problem also has an FP32
+// residual r32 and two FP32 correction buffers e0 / e1, all with the pitch of
+// x.  Work items: 2D tiles, 1D tile groups; a refinement step splits the grid
+// into blocks (2D 64 columns x 32 rows, 1D 2048 points) dealt round-robin to
+// the problem's work items.
 struct BProb {
-    int32_t dim;     // 1 or 2
-    int32_t pad;
-    Geom2 g2;        // dim 2
-    Geom1 g1;        // dim 1
+    int32_t dim;         // 1 or 2
+    int32_t dt;          // F64 / F32: precision of f and x (the main cycles)
+    Geom2 g2;            // dim 2
+    Geom1 g1;            // dim 1
     const void *f;
     void *x;
     void *s1;
-    int64_t item0;   // first work item of this problem in its dimension's list
-    int64_t nitems;  // work items: 2D tiles, or 1D tile groups
-    int64_t part0;   // first residual partial slot
-    double tol;      // relative tolerance (<= 0: run max_cycles cycles)
-    int64_t max_cycles;  // this problem stops running after iterate max_cycles
+    float *r32, *e0, *e1;  // refined problems only
+    int64_t item0;       // first work item of this problem in its list
+    int64_t nitems;      // work items
+    int64_t part0;       // first partial slot (one per work item)
+    int64_t rnitems;     // refinement-step blocks
+    double tol;          // relative tolerance (<= 0: run max_cycles cycles)
+    int64_t max_cycles;  // cycles a result may take (all phases together)
+    int32_t s;           // sweeps per cycle
+    int32_t pad;
 };
 
-struct BCtl {
-    int64_t cycle;       // cycle the next kernels run (advanced on the device)
-    int64_t max_cycles;  // largest per-problem cap (replays run to it)
+// Phases of a problem.  MAIN: cycles of the problem's own precision on x.
+// INNER: FP32 cycles on the correction equation A e = r32.  REF: one step of
+// refinement (x += e, the FP64 residual of the new x, r32 and a cleared
+// correction for the next INNER phase) in place of a cycle; `next` says what
+// follows it (END: nothing, the budget is spent).
+enum : int32_t { PH_MAIN = 0, PH_INNER = 1, PH_REF = 2, PH_END = 3 };
+
+// Per-problem state, written by the judge (and init) only.
+struct BState {
+    double r0sq;      // ||f - A x_0||^2
+    double rsq;       // ||f - A x||^2 of the latest FP64-judged x
+    double in_tolsq;  // INNER: stop once ||r32 - A e_j||^2 <= in_tolsq
+    double mark_rsq;  // MAIN: residual where the rate measurement starts; INNER: last halving
+    double lnrate;    // ln of the per-cycle residual factor at the switch (0: unknown)
+    int64_t j;        // iterate of the current phase that the next cycle reads
+    int64_t mark_j;   // cycle of mark_rsq (-1: none)
+    int64_t used;     // cycles inside the result (closed phases)
+    int32_t status;   // ST_*
+    int32_t phase;    // PH_*
+    int32_t xsel;     // main buffer holding iterate 0 of the main phase, or the refined x
+    int32_t esel;     // inner buffer holding iterate 0 of the inner phase
+    int32_t rx;       // REF: main buffer with x (the new x goes to xsel)
+    int32_t esrc;     // REF: inner buffer with e (-1: none)
+    int32_t next;     // REF: phase after the step
+    int32_t outer;    // correction solves taken
+    int32_t cont;     // main phase runs to rel_tol (no switch to FP32)
+    int32_t pad;
+};
+
+// Refinement settings of a batch (refine = 0: plain solves).
+struct BRefine {
+    int32_t refine;
+    int32_t max_outer;  // correction solves per problem; then it continues in FP64
+    double switch_tol;  // MAIN -> refinement at most at this relative residual
+    double inner_min;   // least relative reduction one correction solve is asked for
+    double fmax;        // predicted FP32 floor above which a problem stays FP64
 };
 
 struct BatchLaunch {
     const BProb *probs;
     const int32_t *owner;  // problem of each work item
     int64_t nitems;
-    const BCtl *bc;
-    const Ctrl *ctrl;      // one per problem
-    double *part;          // 2 x npart partial slots (by cycle parity)
-    int64_t npart;
+    const BState *state;   // one per problem
+    double *part;          // one partial slot per work item
     int s;
 };
 
-// One problem of a batched refinement step: FP64 f, x (pitch ld), FP32
-// residual and correction (pitch nx).  Work items: 2D blocks of 64 columns x
-// 32 rows, 1D blocks of 2048 points.
-struct BRef {
-    int32_t dim;
-    int32_t nx, ny;
-    int32_t pad;
-    int64_t ld;
-    double wx, wy;   // 1 / hx^2, 1 / hy^2 (1D: wx)
-    const double *f;
-    double *x;
-    float *r32;
-    float *e32;
-    int64_t item0;   // first work item of this problem
-    int64_t nitems;
-    int64_t part0;   // first partial slot
-};
-
 int64_t ref_items(int dim, int64_t nx, int64_t ny);
-// r32 = f - A x (FP64, stored FP32), e32 = 0, partials of ||r||^2 per item
-hipError_t launch_batch_ref_resid(const BRef *refs, const int32_t *owner, int64_t nitems, double *part,
-                                  hipStream_t st);
-// rsq[p] = sum of problem p's partials (fixed order)
-hipError_t launch_batch_ref_norm(const BRef *refs, int nref, const double *part, double *rsq,
-                                 hipStream_t st);
-// x += (double) e32 over the listed items
-hipError_t launch_batch_ref_axpy(const BRef *refs, const int32_t *owner, int64_t nitems, hipStream_t st);
-
 bool batch2d_supported(int tx, int ty);
-// iso: the work list holds only problems with hx == hy (else only the others)
-hipError_t launch_batch_cycle2d(int dt, int tx, int ty, bool iso, const BatchLaunch &L, hipStream_t st);
-hipError_t launch_batch_cycle1d(int dt, int t, const BatchLaunch &L, hipStream_t st);
-hipError_t launch_batch_judge(const BProb *probs, int nprob, const BCtl *bc, Ctrl *ctrl,
-                              const double *part, int64_t npart, hipStream_t st);
-hipError_t launch_batch_advance(BCtl *bc, hipStream_t st);
-hipError_t launch_batch_init(Ctrl *ctrl, int nprob, BCtl *bc, int64_t max_cycles, hipStream_t st);
-hipError_t launch_batch_finalize(int dt, const BProb *probs, int nprob, const Ctrl *ctrl,
-                                 hipStream_t st);
+// iso: the work list holds only problems with hx == hy (else only the others).
+// Plain batches run cycles of precision dt; refined ones (FP64 problems) run
+// each problem's phase: FP64 main cycle, FP32 inner cycle or refinement step.
+hipError_t launch_batch_cycle2d(int dt, bool refine, int tx, int ty, bool iso, const BatchLaunch &L,
+                                hipStream_t st);
+hipError_t launch_batch_cycle1d(int dt, bool refine, int t, const BatchLaunch &L, hipStream_t st);
+hipError_t launch_batch_judge(const BProb *probs, int nprob, BState *state, const double *part,
+                              const BRefine &rf, hipStream_t st);
+hipError_t launch_batch_init(BState *state, int nprob, hipStream_t st);
+// copies each stopped problem's result into x when it sits in buffer 1
+hipError_t launch_batch_finalize(const BProb *probs, int nprob, const BState *state, hipStream_t st);
 
+// mixed precision helpers (hj_refine.hip)
 int64_t resid2d_mixed_blocks(const Geom2 &g);
 hipError_t launch_resid2d_f64_to_f32(const Geom2 &g, const double *f, const double *x, float *r32,
                                      float *e32, double *part, hipStream_t st);

@@ -217,7 +217,7 @@ def test_refined_batch_cycle_cap_covers_all_phases():
         r = residual_np(kind, f, got[i], hx, hy if hy else hx)
         say(f"capped refined batch[{i}] {kind} {f.shape}: cycles {infos[i].cycles}, rel {r:.2e}")
         assert 0 < infos[i].cycles <= cap
-        assert abs(infos[i].rel_residual - r) <= 1e-6 * r
+        assert abs(infos[i].rel_residual - r) <= 1e-6 * r + 1e-13  # FP64 rounding of the two residuals
         if infos[i].status == hj.HJ_OK:
             assert r <= 1.001e-10
         else:
