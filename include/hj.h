@@ -216,21 +216,28 @@ typedef struct hj_batch_params {
     int32_t graph_cycles; /* cycles per graph replay, 0 = 8, at most 1024 */
     int32_t flags;        /* HJ_BATCH_AUTOTUNE: choose p2 and p1 with hj_autotune (2D on the
                              largest 2D problem, tiles limited to the smallest);
-                             HJ_BATCH_REFINE: FP64 problems (dtype HJ_F64, rel_tol > 0) solved
-                             as hj_solve_2d_refined does: FP64 cycles down to
-                             min(1, 1e4 * rel_tol), then refinement steps of FP32 correction
-                             cycles, each problem stopping at its own rel_tol */
-    int32_t max_outer;    /* HJ_BATCH_REFINE: refinement steps allowed (0 = 8) */
+                             HJ_BATCH_REFINE: FP64 problems (dtype HJ_F64, rel_tol > 0), each on
+                             its own schedule: FP64 cycles down to min(1e4 rel_tol,
+                             rel_tol / 8F) (F the problem's FP32 floor predicted from its
+                             measured convergence rate), then refinement steps (x += e and
+                             the FP64 residual in one pass) around FP32 correction cycles;
+                             a problem whose F exceeds 1/80, or whose correction solve stops
+                             converging, continues with FP64 cycles */
+    int32_t max_outer;    /* HJ_BATCH_REFINE: FP32 correction solves per problem (0 = 8);
+                             after them a problem continues with FP64 cycles */
 } hj_batch_params;
 
-/* Scratch: one iterate array per problem (the sum of the problems' sizes),
- * partials and control blocks, kept per device and grown on demand.  infos
+/* Scratch: one iterate array per problem (the sum of the problems' sizes;
+ * refined batches add an FP32 residual and two FP32 correction arrays per
+ * problem), partials and per-problem states, kept per device and grown on
+ * demand.  infos[i].cycles counts the cycles inside problem i's result (FP64
+ * and FP32 together when refined).  infos
  * (nprob entries) may be NULL; problem i met rel_tol iff
  * infos[i].rel_residual <= rel_tol (NaN: its residual became non-finite).
  * Problems must not share x arrays.  Returns HJ_OK when every problem met rel_tol
  * (or ran max_cycles in fixed-count mode), HJ_ERR_NOT_CONVERGED if some
- * stopped at max_cycles or, refined, after max_outer steps (their latest
- * iterate is in x), HJ_ERR_NONFINITE if some residual became non-finite. */
+ * stopped at max_cycles (their latest iterate is in x), HJ_ERR_NONFINITE if
+ * some residual became non-finite. */
 hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batch_params *p,
                            void *stream, hj_info *infos);
 

@@ -126,17 +126,24 @@ __global__ __launch_bounds__(64 * W) void k_batch_cycle2d(const BProb *__restric
         main_arrays<float>(P, S, xin, xout);
         rsq = reg_tile_2d<float, C, R, W, true, ISO, rotate_rows<float>()>(P.g2, tile, (const float *)P.f, xin,
                                                                           xout, s);
-    } else if (M == BM_F64 || S.phase == PH_MAIN) {
+    } else if (M == BM_F64) {
         const double *xin;
         double *xout;
         main_arrays<double>(P, S, xin, xout);
         rsq = reg_tile_2d<double, C, R, W, true, ISO, rotate_rows<double>()>(P.g2, tile, (const double *)P.f,
                                                                             xin, xout, s);
+    } else if (S.phase == PH_MAIN) {
+        // refined: both precisions share one LDS pool sized for FP64
+        const double *xin;
+        double *xout;
+        main_arrays<double>(P, S, xin, xout);
+        rsq = reg_tile_2d<double, C, R, W, true, ISO, rotate_rows<double>(), 8>(P.g2, tile, (const double *)P.f,
+                                                                               xin, xout, s);
     } else if (S.phase == PH_INNER) {
         const float *ein;
         float *eout;
         inner_arrays(P, S, ein, eout);
-        rsq = reg_tile_2d<float, C, R, W, true, ISO, rotate_rows<float>()>(P.g2, tile, P.r32, ein, eout, s);
+        rsq = reg_tile_2d<float, C, R, W, true, ISO, rotate_rows<float>(), 8>(P.g2, tile, P.r32, ein, eout, s);
     } else {
         rsq = ref_blocks<NT>(P, S, tile, P.nitems);
     }

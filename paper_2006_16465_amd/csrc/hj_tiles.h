@@ -111,19 +111,44 @@ __device__ __forceinline__ float fma_quarter(float sv, float b)
     return r;
 }
 
+// LDS of BYTES bytes; every caller asking for the same size gets the same
+// array, so a kernel that runs reg_tile_2d in two precisions (never both in
+// one workgroup) can size it for the wider one and hold it once.
+template <int BYTES>
+__device__ __forceinline__ char *lds_pool()
+{
+    __shared__ __align__(16) char pool[BYTES];
+    return pool;
+}
+
 // One cycle of tile `tile` (row-major tile index over g's partition) by a
 // workgroup of 64 W threads.  Returns this thread's share of ||r||^2 of xin
 // over the owned points (RES), else 0.  A caller that runs several tiles in a
-// row must place a barrier between them (LDS is reused).
-template <typename T, int C, int R, int W, bool RES, bool ISO, bool ROT>
+// row must place a barrier between them (LDS is reused).  LB = 0: LDS arrays
+// of this instantiation; LB > 0: the lds_pool sized for LB-byte elements.
+template <typename T, int C, int R, int W, bool RES, bool ISO, bool ROT, int LB = 0>
 __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T *__restrict__ f,
                                               const T *__restrict__ xin, T *__restrict__ xout,
                                               int nsub)
 {
     constexpr int TX = 16 * C, TY = 4 * R * W, NG = 4 * W;
-    __shared__ T s_top[2][NG][TX];  // first row of each row group, by sweep parity
-    __shared__ T s_bot[2][NG][TX];  // last row of each row group
-    __shared__ T s_halo[2][TX];     // frozen rows -1 and TY
+    T(*s_top)[NG][TX];  // first row of each row group, by sweep parity
+    T(*s_bot)[NG][TX];  // last row of each row group
+    T(*s_halo)[TX];     // frozen rows -1 and TY
+    if constexpr (LB == 0) {
+        __shared__ T a_top[2][NG][TX];
+        __shared__ T a_bot[2][NG][TX];
+        __shared__ T a_halo[2][TX];
+        s_top = a_top;
+        s_bot = a_bot;
+        s_halo = a_halo;
+    } else {
+        static_assert(LB >= (int)sizeof(T), "LDS pool sized for narrower elements");
+        char *pool = lds_pool<(4 * NG * TX + 2 * TX) * LB>();
+        s_top = reinterpret_cast<T(*)[NG][TX]>(pool);
+        s_bot = reinterpret_cast<T(*)[NG][TX]>(pool + 2 * NG * TX * sizeof(T));
+        s_halo = reinterpret_cast<T(*)[TX]>(pool + 4 * NG * TX * sizeof(T));
+    }
 
     const int k = (int)threadIdx.x >> 4, j = (int)threadIdx.x & 15;
     const int bi = tile / g.ntx, bj = tile - bi * g.ntx;
