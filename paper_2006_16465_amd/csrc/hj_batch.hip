@@ -168,17 +168,17 @@ __global__ __launch_bounds__(kNT) void k_batch_cycle1d(const BProb *__restrict__
         const float *xin;
         float *xout;
         main_arrays<float>(P, S, xin, xout);
-        rsq = lds_tiles_1d<float, TT, true>(P.g1, blk, (const float *)P.f, xin, xout, s);
+        rsq = tiles_1d<float, TT, true>(P.g1, blk, (const float *)P.f, xin, xout, s);
     } else if (M == BM_F64 || S.phase == PH_MAIN) {
         const double *xin;
         double *xout;
         main_arrays<double>(P, S, xin, xout);
-        rsq = lds_tiles_1d<double, TT, true>(P.g1, blk, (const double *)P.f, xin, xout, s);
+        rsq = tiles_1d<double, TT, true>(P.g1, blk, (const double *)P.f, xin, xout, s);
     } else if (S.phase == PH_INNER) {
         const float *ein;
         float *eout;
         inner_arrays(P, S, ein, eout);
-        rsq = lds_tiles_1d<float, TT, true>(P.g1, blk, P.r32, ein, eout, s);
+        rsq = tiles_1d<float, TT, true>(P.g1, blk, P.r32, ein, eout, s);
     } else {
         rsq = ref_blocks<kNT>(P, S, blk, P.nitems);
     }

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kNT) void k_cycle1d(Geom1 g, const T *__restrict__ 
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
-    const double rsq = lds_tiles_1d<T, TT, RES>(g, xcd_tile(blockIdx.x, gridDim.x), f, xin, xout, s);
+    const double rsq = tiles_1d<T, TT, RES>(g, xcd_tile(blockIdx.x, gridDim.x), f, xin, xout, s);
     if (RES) post_partial<kNT>(rsq, red.part_cur);
 }
 
@@ -335,8 +335,7 @@ template <typename T, int TT>
 hipError_t cyc1(const Geom1 &g, int s, bool res, const void *f, const void *xin, void *xout,
                 const Red &red, double tol, hipStream_t st)
 {
-    constexpr int G = TT <= kNT ? kNT / TT : 1;
-    const unsigned nb = (unsigned)((g.nt + G - 1) / G);
+    const unsigned nb = (unsigned)cycle1d_blocks(g);  // the count the judge sums partials over
     if (res) k_cycle1d<T, TT, true><<<nb, kNT, 0, st>>>(g, (const T *)f, (const T *)xin, (T *)xout, s, red, tol);
     else k_cycle1d<T, TT, false><<<nb, kNT, 0, st>>>(g, (const T *)f, (const T *)xin, (T *)xout, s, red, tol);
     return hipGetLastError();
@@ -392,7 +391,7 @@ int64_t resid2d_blocks(const Geom2 &g) { return sweep2d_blocks(g); }
 
 int64_t cycle1d_blocks(const Geom1 &g)
 {
-    const int64_t G = g.t <= kNT ? kNT / g.t : 1;
+    const int64_t G = tiles_per_block_1d(g.t);
     return (g.nt + G - 1) / G;
 }
 

@@ -457,6 +457,163 @@ __device__ __forceinline__ double lds_tiles_1d(const Geom1 &g, int64_t blk, cons
 }
 
 
+// ============================================================================
+// 1D hierarchical cycle, register-resident (TT a multiple of 64).  One
+// wavefront per tile of TT = 64 P points: lane L holds points [L P, L P + P)
+// of the tile in VGPRs; the neighbours of a lane's first and last points come
+// from the lanes beside it through DPP whole-wavefront shifts, and lanes 0 and
+// 63 take the frozen halo instead.  No LDS and no barrier: the four
+// wavefronts of a workgroup run four tiles on their own.  Same update and
+// residual expressions as lds_tiles_1d, so the iterates are the same bit for
+// bit.
+// ============================================================================
+constexpr int kDppWaveShr1 = 0x138;  // lane i <- lane i - 1 of the wavefront
+constexpr int kDppWaveShl1 = 0x130;  // lane i <- lane i + 1 of the wavefront
+constexpr int kRegTiles1d = kNT / 64;  // tiles per workgroup
+
+// Lanes whose source falls outside the wavefront keep `old`.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double old, double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long o = __builtin_bit_cast(unsigned long long, old);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi =
+        __builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float old, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                  __builtin_bit_cast(int, v), CTRL, 0xf, 0xf,
+                                                                  false));
+}
+
+// One sweep from a to b: b_i = (h^2 f_i + (a_{i-1} + a_{i+1})) / 2 in the FMA
+// form fma(a_{i-1} + a_{i+1}, 1/2, h^2 f_i / 2) (equal bit for bit while the
+// values are normal numbers: halving is exact and commutes with rounding).
+template <typename T, int P, bool MASK>
+__device__ __forceinline__ void reg_sweep_1d(const T (&a)[P], T (&b)[P], const T (&fh)[P], T haloL, T haloR,
+                                             int l0, int ni)
+{
+    const T lft = dpp_move<kDppWaveShr1>(haloL, a[P - 1]);
+    const T rgt = dpp_move<kDppWaveShl1>(haloR, a[0]);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const T w = i > 0 ? a[i - 1] : lft;
+        const T e = i + 1 < P ? a[i + 1] : rgt;
+        T v = __builtin_fma(w + e, T(0.5), fh[i]);
+        if (MASK) v = l0 + i < ni ? v : T(0);
+        b[i] = v;
+    }
+}
+
+// The cycle of one tile by its wavefront: load, residual of the incoming
+// iterate over the owned points (RES), s sweeps ping-ponging two register
+// arrays, write-back.  MASK: the grid is shorter than the tile (ni < TT
+// points); points at or past ni read and stay 0.
+template <typename T, int P, bool RES, bool MASK>
+__device__ __forceinline__ double reg_tile_1d(const Geom1 &g, const T *__restrict__ fp, const T *__restrict__ xp,
+                                              T *__restrict__ op, T haloL, T haloR, int l0, int ni, int lo,
+                                              int hi, int s)
+{
+    const T hh = T(g.hh);
+    T xa[P], xb[P], fh[P];
+    double rsq = 0.0;
+    {
+        T fv[P];
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const bool in = !MASK || l0 + i < ni;
+            xa[i] = in ? xp[i] : T(0);
+            fv[i] = in ? fp[i] : T(0);
+        }
+        if (RES) {
+            const T lft = dpp_move<kDppWaveShr1>(haloL, xa[P - 1]);
+            const T rgt = dpp_move<kDppWaveShl1>(haloR, xa[0]);
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+                const int lc = l0 + i;
+                if (lc >= lo && lc < hi) {
+                    const double w = i > 0 ? (double)xa[i - 1] : (double)lft;
+                    const double e = i + 1 < P ? (double)xa[i + 1] : (double)rgt;
+                    const double rr = res1((double)fv[i], (double)xa[i], w, e, g.w1);
+                    rsq += rr * rr;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) fh[i] = (hh * fv[i]) * T(0.5);
+    }
+    int k = 0;
+    for (; k + 1 < s; k += 2) {
+        reg_sweep_1d<T, P, MASK>(xa, xb, fh, haloL, haloR, l0, ni);
+        reg_sweep_1d<T, P, MASK>(xb, xa, fh, haloL, haloR, l0, ni);
+    }
+    if (k < s) {
+        reg_sweep_1d<T, P, MASK>(xa, xb, fh, haloL, haloR, l0, ni);
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int lc = l0 + i;
+            if (lc >= lo && lc < hi) op[i] = xb[i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int lc = l0 + i;
+            if (lc >= lo && lc < hi) op[i] = xa[i];
+        }
+    }
+    return rsq;
+}
+
+// One cycle of the tiles of workgroup `blk` (tiles blk*4 .. blk*4 + 3, one
+// per wavefront).  Returns this thread's share of ||r||^2 of xin over the
+// owned points (RES), else 0.
+template <typename T, int TT, bool RES>
+__device__ __forceinline__ double reg_tiles_1d(const Geom1 &g, int64_t blk, const T *__restrict__ f,
+                                               const T *__restrict__ xin, T *__restrict__ xout, int s)
+{
+    constexpr int P = TT / 64;
+    static_assert(TT % 64 == 0 && P >= 1, "register 1D tiles hold 64 P points");
+    const int lane = (int)threadIdx.x & 63;
+    const int64_t tile = blk * kRegTiles1d + ((int)threadIdx.x >> 6);
+    const int ntile = (int)g.nt;
+    if (tile >= ntile) return 0.0;
+
+    const int64_t n = g.n;
+    const int nint = n > 0x7fffffff ? 0x7fffffff : (int)n;
+    const int ni = n < TT ? (int)n : TT;  // points per tile
+    const int64_t x0 = axis_origin(nint, TT, g.o, (int)tile);
+    const int lo = axis_own_begin(nint, TT, g.o, (int)tile) - (int)x0;
+    const int hi = axis_own_end(nint, TT, g.o, (int)tile, ntile) - (int)x0;
+    const int l0 = lane * P;
+    const T haloL = x0 > 0 ? xin[x0 - 1] : T(0);
+    const T haloR = x0 + TT < n ? xin[x0 + TT] : T(0);
+    const int64_t a = x0 + l0;
+    if (ni == TT) return reg_tile_1d<T, P, RES, false>(g, f + a, xin + a, xout + a, haloL, haloR, l0, ni, lo, hi, s);
+    return reg_tile_1d<T, P, RES, true>(g, f + a, xin + a, xout + a, haloL, haloR, l0, ni, lo, hi, s);
+}
+
+
+// Tiles per workgroup of the 1D cycle, and its body: register-resident for
+// tiles of 64 points and more, LDS below.
+__host__ __device__ constexpr int tiles_per_block_1d(int tt)
+{
+    return tt % 64 == 0 ? kRegTiles1d : (tt <= kNT ? kNT / tt : 1);
+}
+
+template <typename T, int TT, bool RES>
+__device__ __forceinline__ double tiles_1d(const Geom1 &g, int64_t blk, const T *__restrict__ f,
+                                           const T *__restrict__ xin, T *__restrict__ xout, int s)
+{
+    if constexpr (TT % 64 == 0) return reg_tiles_1d<T, TT, RES>(g, blk, f, xin, xout, s);
+    else return lds_tiles_1d<T, TT, RES>(g, blk, f, xin, xout, s);
+}
+
+
 // Register-resident shape for a TX x TY tile: C columns and R rows per lane,
 // W wavefronts.  Up to 32 x 32 one wavefront holds the tile (R = TY / 4);
 // taller tiles use 4 rows per lane (8 at TX = 32) and more wavefronts, which

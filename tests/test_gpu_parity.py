@@ -221,9 +221,12 @@ def test_global_sweep_2d_matches_oracle(orc, shape):
 # ------------------------------------------------------------------ 1D
 
 @pytest.mark.parametrize("n", [256, 1000, 37, 5, 3000])
-@pytest.mark.parametrize("tile", [32, 64, 256, 1024])
+@pytest.mark.parametrize("tile", [32, 64, 128, 256, 512, 1024])
 @pytest.mark.parametrize("overlap", [0, 4, 10])
 def test_cycle1d_matches_oracle(orc, n, tile, overlap):
+    """Tiles of 64 points and more run register-resident (one wavefront per
+    tile), 32-point tiles through LDS; both must equal the oracle bit for bit,
+    also on grids shorter than one tile."""
     f = W.rhs_random(n, n + tile)
     x0 = W.rhs_random(n, n + tile + 1)
     h = 1.0 / (n + 1)
@@ -285,6 +288,22 @@ def test_solve_1d_cycles_to_tol_match_oracle(orc, seed):
         assert np.array_equal(host(X), xo)
         assert abs(info.rel_residual - relo) <= 1e-12 * relo
         assert abs(info.r0_norm - r0o) <= 1e-12 * r0o
+
+
+@pytest.mark.parametrize("n,tile,s,ov", [(256, 64, 8, 14), (5000, 512, 24, 46), (70000, 1024, 24, 46)])
+def test_solve_1d_overlapped_register_tiles_to_tol_match_oracle(orc, n, tile, s, ov):
+    """Exact-regime overlap (o = 2s - 2) with register-resident tiles, solved
+    to 1e-6 from x0 = 0: same cycle count and iterate as the oracle."""
+    f = W.rhs_1d_modes(n, 8, 11)
+    h = 1.0 / (n + 1)
+    x0 = np.zeros_like(f)
+    X = dev(x0)
+    say(f"solve1d n={n} tile={tile} s={s} ov={ov}")
+    info = hj.solve_1d(dev(f), X, h, tile=tile, s=s, overlap=ov, rel_tol=1e-6)
+    xo, co, relo, _ = orc.solve_1d(f, x0, h, tile=tile, s=s, tol=1e-6, overlap=ov)
+    assert info.cycles == co > 0
+    assert np.array_equal(host(X), xo)
+    assert abs(info.rel_residual - relo) <= 1e-12 * relo
 
 
 @pytest.mark.parametrize("s,tile,ov", [(8, (32, 32), (0, 0)), (16, (32, 32), (0, 0)), (4, (16, 16), (2, 2))])
