@@ -594,7 +594,7 @@ hj_status check_problem(const hj_problem &q, hj_dtype dt, int dev, int64_t i)
 // and each x its result.  Device and lock held by the caller.
 hj_status run_batch(const hj_problem *probs, int64_t nprob, hj_dtype dt, double tol, int64_t max_cycles,
                     const hj::BRefine &rf, const hj_params &P2, const hj_params &P1, int K, hipStream_t st,
-                    DevScratch &S, BatchScratch &B)
+                    DevScratch &S, BatchScratch &B, const hj::GeomVC *vc = nullptr)
 {
     const int idt = dt == HJ_F64 ? hj::F64 : hj::F32;
     const size_t es = esize(dt);
@@ -619,6 +619,11 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, hj_dtype dt, double 
         if (q.dim == 2) {
             b.g2 = make_geom2(q.nx, q.ny, q.ld, q.hx, q.hy, P2);
             b.nitems = (int64_t)b.g2.ntx * b.g2.nty;
+            b.s = P2.s;
+            elems = q.ny * q.ld;
+        } else if (q.dim == 3) {
+            b.gv = *vc;
+            b.nitems = hj::cycle_vc_blocks(b.gv);
             b.s = P2.s;
             elems = q.ny * q.ld;
         } else {
@@ -684,7 +689,7 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, hj_dtype dt, double 
     // long-running problems does not pay for launching everyone else's
     // finished tiles.  The caller's stream is idle whenever this runs.
     std::vector<int32_t> own;
-    int64_t n_iso = 0, n_gen = 0, n_1d = 0;
+    int64_t n_iso = 0, n_gen = 0, n_1d = 0, n_vc = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     auto cleanup = [&]() {
@@ -695,16 +700,16 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, hj_dtype dt, double 
     };
     auto rebuild = [&](const hj::BState *snap) -> hj_status {
         own.clear();
-        for (int pass = 0; pass < 3; ++pass) {
+        for (int pass = 0; pass < 4; ++pass) {
             const int64_t start = (int64_t)own.size();
             for (int64_t i = 0; i < nprob; ++i) {
                 hj::BProb &b = hp[(size_t)i];
-                const int kind = b.dim == 1 ? 2 : (b.g2.iso ? 0 : 1);
+                const int kind = b.dim == 1 ? 2 : b.dim == 3 ? 3 : (b.g2.iso ? 0 : 1);
                 if (kind != pass || (snap && snap[i].status != hj::ST_RUNNING)) continue;
                 b.item0 = (int64_t)own.size() - start;
                 own.insert(own.end(), (size_t)b.nitems, (int32_t)i);
             }
-            (pass == 0 ? n_iso : pass == 1 ? n_gen : n_1d) = (int64_t)own.size() - start;
+            (pass == 0 ? n_iso : pass == 1 ? n_gen : pass == 2 ? n_1d : n_vc) = (int64_t)own.size() - start;
         }
         HJ_HIP(hipMemcpyAsync(B.probs, hp.data(), hp.size() * sizeof(hj::BProb), hipMemcpyHostToDevice, st));
         if (!own.empty())
@@ -714,12 +719,14 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, hj_dtype dt, double 
         const hj::BatchLaunch Li{B.probs, B.owner, n_iso, B.state, B.part, P2.s};
         const hj::BatchLaunch Lg{B.probs, B.owner + n_iso, n_gen, B.state, B.part, P2.s};
         const hj::BatchLaunch L1{B.probs, B.owner + n_iso + n_gen, n_1d, B.state, B.part, P1.s};
+        const hj::BatchLaunch Lv{B.probs, B.owner + n_iso + n_gen + n_1d, n_vc, B.state, B.part, P2.s};
         HJ_HIP(hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
         for (int k = 0; k < K && ce == hipSuccess; ++k) {
             if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, refine, P2.tile_x, P2.tile_y, true, Li, B.cap);
             if (ce == hipSuccess) ce = hj::launch_batch_cycle2d(idt, refine, P2.tile_x, P2.tile_y, false, Lg, B.cap);
             if (ce == hipSuccess) ce = hj::launch_batch_cycle1d(idt, refine, P1.tile_x, L1, B.cap);
+            if (ce == hipSuccess) ce = hj::launch_batch_cycle_vc(P2.tile_x, P2.tile_y, Lv, B.cap);
             if (ce == hipSuccess) ce = hj::launch_batch_judge(B.probs, (int)nprob, B.state, B.part, rf, B.cap);
         }
         const hipError_t ee = hipStreamEndCapture(B.cap, &graph);
@@ -784,6 +791,57 @@ hj_status run_batch(const hj_problem *probs, int64_t nprob, hj_dtype dt, double 
     if (le == hipSuccess) le = hipStreamSynchronize(st);
     cleanup();
     if (le != hipSuccess) return hip_fail(le, "batch replay");
+    return HJ_OK;
+}
+
+// Several right-hand sides of one variable-coefficient operator: each is a
+// problem of the batched engine (one launch per cycle for all of them, each
+// judged on its own), so every right-hand side gets the iterates and the
+// cycle count of its own solve.
+hj_status solve_vc_batched(const hj_vc_problem &pr, const double *f, double *u, const hj_params &P,
+                           hipStream_t st, int dev, DevScratch &S, hj_info *infos)
+{
+    if (!hj::batch_vc_supported(P.tile_x ? P.tile_x : 32, P.tile_y ? P.tile_y : 32))
+        return fail(HJ_ERR_UNSUPPORTED, "variable-coefficient tile shape");
+    const hj::GeomVC g = make_geom_vc(pr, P);
+    std::vector<hj_problem> probs((size_t)pr.batch);
+    for (int b = 0; b < pr.batch; ++b) {
+        hj_problem &q = probs[(size_t)b];
+        std::memset(&q, 0, sizeof(q));
+        q.dim = 3;
+        q.nx = pr.nx;
+        q.ny = pr.ny;
+        q.ld = pr.ld;
+        q.hx = pr.hx;
+        q.hy = pr.hy;
+        q.f = f + (int64_t)b * pr.batch_stride;
+        q.x = u + (int64_t)b * pr.batch_stride;
+    }
+    hj_params P2 = P, P1;
+    P2.tile_x = g.tx;
+    P2.tile_y = g.ty;
+    hj_params_default(&P1);
+    const double tol = P.rel_tol > 0.0 ? P.rel_tol : -1.0;
+    BatchScratch &B = g_bat[dev];
+    hj_status r;
+    if ((r = run_batch(probs.data(), pr.batch, HJ_F64, tol, P.max_cycles, hj::BRefine{}, P2, P1, 8, st, S, B,
+                       &g)) != HJ_OK)
+        return r;
+    hj_status worst = HJ_OK;
+    for (int b = 0; b < pr.batch; ++b) {
+        const hj::BState &c = B.host[b];
+        if (infos) {
+            infos[b].cycles = c.used;
+            infos[b].sweeps = c.used * P.s;
+            infos[b].r0_norm = std::sqrt(c.r0sq);
+            infos[b].rel_residual = c.r0sq > 0.0 ? std::sqrt(c.rsq) / std::sqrt(c.r0sq) : 0.0;
+            if (!std::isfinite(c.rsq)) infos[b].rel_residual = NAN;
+        }
+        if (c.status == hj::ST_NONFINITE) worst = HJ_ERR_NONFINITE;
+        else if (c.status != hj::ST_CONVERGED && tol > 0.0 && worst == HJ_OK) worst = HJ_ERR_NOT_CONVERGED;
+    }
+    if (worst == HJ_ERR_NONFINITE) return fail(worst, "residual norm became non-finite");
+    if (worst == HJ_ERR_NOT_CONVERGED) return fail(worst, "max_cycles reached before rel_tol");
     return HJ_OK;
 }
 
@@ -1267,6 +1325,8 @@ hj_status hj_solve_vc_2d(const hj_vc_problem *prob, const double *f, double *u, 
     if ((r = check_device_ptr(u, dev, "u")) != HJ_OK) return r;
     DevScratch &S = g_scr[dev];
     std::lock_guard<std::mutex> lock(S.mu);
+    if (p->method == HJ_HIERARCHICAL && prob->batch > 1)
+        return solve_vc_batched(*prob, f, u, *p, (hipStream_t)stream, dev, S, infos);
     return solve_vc_locked(*prob, f, u, *p, (hipStream_t)stream, S, infos);
 }
 

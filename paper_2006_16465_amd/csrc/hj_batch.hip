@@ -8,6 +8,8 @@
 //                    iterate j into the other buffer, the residual of
 //                    iterate j fused into the load (per-tile partials);
 //   k_batch_cycle1d  the same for the 1D tile groups (Sec. 3.3);
+//   k_batch_cycle_vc the same for variable-coefficient 2D problems (the
+//                    right-hand sides of one diffusion operator);
 //   k_batch_judge    per problem, the partials in a fixed order, the verdict
 //                    on iterate j, and the next phase.
 // Every problem carries its own iterate index and buffer selectors, so
@@ -46,6 +48,7 @@
 
 #include "hj_launch.h"
 #include "hj_tiles.h"
+#include "hj_vc_tile.h"
 
 namespace hj {
 namespace {
@@ -183,6 +186,27 @@ __global__ __launch_bounds__(kNT) void k_batch_cycle1d(const BProb *__restrict__
         rsq = ref_blocks<kNT>(P, S, blk, P.nitems);
     }
     post_partial_at<kNT>(rsq, &part[P.part0 + blk]);
+}
+
+// Variable-coefficient 2D problems (dim 3, FP64, plain): the LDS tile body of
+// the single-problem kernel (hj_vc_tile.h).
+template <int TX, int TY>
+__global__ __launch_bounds__(kNT) void k_batch_cycle_vc(const BProb *__restrict__ probs,
+                                                        const int32_t *__restrict__ owner, int64_t nitems,
+                                                        const BState *__restrict__ state, double *part, int s)
+{
+    const int64_t w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= nitems) return;
+    const int p = owner[w];
+    const BState &S = state[p];
+    if (S.status != ST_RUNNING) return;
+    const BProb &P = probs[p];
+    const double *xin;
+    double *xout;
+    main_arrays<double>(P, S, xin, xout);
+    const int tile = (int)(w - P.item0);
+    const double rsq = lds_tile_vc<TX, TY, true>(P.gv, tile, (const double *)P.f, xin, xout, s);
+    post_partial_at<kNT>(rsq, &part[P.part0 + tile]);
 }
 
 // ---------------------------------------------------------------- judge
@@ -383,9 +407,9 @@ __global__ __launch_bounds__(256) void k_batch_finalize(const BProb *__restrict_
     const int p = (int)blockIdx.x;
     if (result_buf(state[p]) != 1) return;
     const BProb &P = probs[p];
-    const int64_t nx = P.dim == 2 ? P.g2.nx : P.g1.n;
-    const int64_t ny = P.dim == 2 ? P.g2.ny : 1;
-    const int64_t ld = P.dim == 2 ? P.g2.ld : P.g1.n;
+    const int64_t nx = P.dim == 2 ? P.g2.nx : P.dim == 3 ? P.gv.nx : P.g1.n;
+    const int64_t ny = P.dim == 2 ? P.g2.ny : P.dim == 3 ? P.gv.ny : 1;
+    const int64_t ld = P.dim == 2 ? P.g2.ld : P.dim == 3 ? P.gv.ld : P.g1.n;
     const int64_t total = nx * ny;
     for (int64_t i = (int64_t)blockIdx.y * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.y * 256) {
         const int64_t r = i / nx, q = i - r * nx;
@@ -504,7 +528,34 @@ hipError_t bcyc1_m(int t, const BatchLaunch &L, hipStream_t st)
     }
 }
 
+template <int TX, int TY>
+hipError_t bcycvc(const BatchLaunch &L, hipStream_t st)
+{
+    k_batch_cycle_vc<TX, TY><<<(unsigned)L.nitems, kNT, 0, st>>>(L.probs, L.owner, L.nitems, L.state, L.part,
+                                                                  L.s);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+bool batch_vc_supported(int tx, int ty)
+{
+#define HJ_TILE(a, b) \
+    if (tx == a && ty == b) return true;
+    HJ_VC_TILES(HJ_TILE)
+#undef HJ_TILE
+    return false;
+}
+
+hipError_t launch_batch_cycle_vc(int tx, int ty, const BatchLaunch &L, hipStream_t st)
+{
+    if (L.nitems <= 0) return hipSuccess;
+#define HJ_TILE(a, b) \
+    if (tx == a && ty == b) return bcycvc<a, b>(L, st);
+    HJ_VC_TILES(HJ_TILE)
+#undef HJ_TILE
+    return hipErrorInvalidValue;
+}
 
 int64_t ref_items(int dim, int64_t nx, int64_t ny)
 {

@@ -96,10 +96,11 @@ hipError_t launch_grad_a_vc(const GeomVC &g, const double *u, const double *lam,
 // into blocks (2D 64 columns x 32 rows, 1D 2048 points) dealt round-robin to
 // the problem's work items.
 struct BProb {
-    int32_t dim;         // 1 or 2
+    int32_t dim;         // 1, 2, or 3 (2D variable coefficient, FP64, plain)
     int32_t dt;          // F64 / F32: precision of f and x (the main cycles)
     Geom2 g2;            // dim 2
     Geom1 g1;            // dim 1
+    GeomVC gv;           // dim 3
     const void *f;
     void *x;
     void *s1;
@@ -169,6 +170,8 @@ bool batch2d_supported(int tx, int ty);
 hipError_t launch_batch_cycle2d(int dt, bool refine, int tx, int ty, bool iso, const BatchLaunch &L,
                                 hipStream_t st);
 hipError_t launch_batch_cycle1d(int dt, bool refine, int t, const BatchLaunch &L, hipStream_t st);
+bool batch_vc_supported(int tx, int ty);
+hipError_t launch_batch_cycle_vc(int tx, int ty, const BatchLaunch &L, hipStream_t st);
 hipError_t launch_batch_judge(const BProb *probs, int nprob, BState *state, const double *part,
                               const BRefine &rf, hipStream_t st);
 hipError_t launch_batch_init(BState *state, int nprob, hipStream_t st);

@@ -69,6 +69,26 @@ def test_vc_classical_and_tolerance_match_oracle(orc, prob):
         assert abs(infos[b].rel_residual - relo) <= 1e-9 * relo
 
 
+def test_vc_batch_equals_single_rhs_solves(prob):
+    """Several right-hand sides run through the batched engine; each must end
+    where its own single-right-hand-side solve ends: same iterate bit for
+    bit, same cycle count, also when some stop at max_cycles."""
+    nx, ny, hx, hy, a, f = prob
+    opts = dict(hx=hx, hy=hy, tile=(16, 32), s=6, overlap=(10, 10))
+    for tol, cap in ((1e-9, 1_000_000), (1e-9, 40)):
+        U = torch.zeros_like(dev(f))
+        infos = hj.solve_vc_2d(dev(a), dev(f), U, rel_tol=tol, max_cycles=cap, allow_not_converged=True, **opts)
+        for b in range(f.shape[0]):
+            Ub = torch.zeros_like(dev(f[b:b + 1]))
+            one = hj.solve_vc_2d(dev(a), dev(f[b:b + 1]), Ub, rel_tol=tol, max_cycles=cap,
+                                 allow_not_converged=True, **opts)[0]
+            say(f"vc batch b={b} cap={cap}: batched {infos[b].cycles} single {one.cycles}")
+            assert infos[b].cycles == one.cycles <= cap
+            assert np.array_equal(host(U)[b], host(Ub)[0])
+            assert abs(infos[b].rel_residual - one.rel_residual) <= 1e-12 * one.rel_residual
+            assert (infos[b].rel_residual <= tol) == (one.rel_residual <= tol)
+
+
 def test_vc_gradient_matches_oracle_formula(orc, prob):
     nx, ny, hx, hy, a, f = prob
     u = np.stack([W.rhs_random((ny, nx), 20 + b) for b in range(3)])
