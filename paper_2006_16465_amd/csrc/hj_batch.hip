@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kNT) void k_batch_cycle1d(const BProb *__restrict__
 // Variable-coefficient 2D problems (dim 3, FP64, plain): the LDS tile body of
 // the single-problem kernel (hj_vc_tile.h).
 template <int TX, int TY>
-__global__ __launch_bounds__(kNT) void k_batch_cycle_vc(const BProb *__restrict__ probs,
+__global__ __launch_bounds__((vc_threads<TX, TY>())) void k_batch_cycle_vc(const BProb *__restrict__ probs,
                                                         const int32_t *__restrict__ owner, int64_t nitems,
                                                         const BState *__restrict__ state, double *part, int s)
 {
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kNT) void k_batch_cycle_vc(const BProb *__restrict_
     main_arrays<double>(P, S, xin, xout);
     const int tile = (int)(w - P.item0);
     const double rsq = lds_tile_vc<TX, TY, true>(P.gv, tile, (const double *)P.f, xin, xout, s);
-    post_partial_at<kNT>(rsq, &part[P.part0 + tile]);
+    post_partial_at<vc_threads<TX, TY>()>(rsq, &part[P.part0 + tile]);
 }
 
 // ---------------------------------------------------------------- judge
@@ -531,8 +531,8 @@ hipError_t bcyc1_m(int t, const BatchLaunch &L, hipStream_t st)
 template <int TX, int TY>
 hipError_t bcycvc(const BatchLaunch &L, hipStream_t st)
 {
-    k_batch_cycle_vc<TX, TY><<<(unsigned)L.nitems, kNT, 0, st>>>(L.probs, L.owner, L.nitems, L.state, L.part,
-                                                                  L.s);
+    k_batch_cycle_vc<TX, TY><<<(unsigned)L.nitems, vc_threads<TX, TY>(), 0, st>>>(L.probs, L.owner, L.nitems,
+                                                                                  L.state, L.part, L.s);
     return hipGetLastError();
 }
 

@@ -12,18 +12,19 @@ namespace hj {
 namespace {
 
 template <int TX, int TY, bool RES>
-__global__ __launch_bounds__(kNT) void k_cycle2d_vc(GeomVC g, const double *__restrict__ f,
-                                                    const double *__restrict__ xin,
-                                                    double *__restrict__ xout, int nsub, Red red,
-                                                    double tol)
+__global__ __launch_bounds__((vc_threads<TX, TY>())) void k_cycle2d_vc(GeomVC g, const double *__restrict__ f,
+                                                                    const double *__restrict__ xin,
+                                                                    double *__restrict__ xout, int nsub,
+                                                                    Red red, double tol)
 {
+    constexpr int NT = vc_threads<TX, TY>();
     if (RES) {
         if (stopped(red.ctrl, red.c)) return;
         if (blockIdx.x == 0 && red.nb_prev > 0)
-            judge_partials<kNT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
+            judge_partials<NT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
     const double rsq = lds_tile_vc<TX, TY, RES>(g, xcd_tile(blockIdx.x, gridDim.x), f, xin, xout, nsub);
-    if (RES) post_partial<kNT>(rsq, red.part_cur);
+    if (RES) post_partial<NT>(rsq, red.part_cur);
 }
 
 // classical sweep (SWEEP) and / or residual (RES; with r_out when !SWEEP)
@@ -100,8 +101,9 @@ hipError_t cyc_vc(const GeomVC &g, int s, bool res, const double *f, const doubl
                   const Red &red, double tol, hipStream_t st)
 {
     const unsigned nb = (unsigned)((int64_t)g.ntx * g.nty);
-    if (res) k_cycle2d_vc<TX, TY, true><<<nb, kNT, 0, st>>>(g, f, xin, xout, s, red, tol);
-    else k_cycle2d_vc<TX, TY, false><<<nb, kNT, 0, st>>>(g, f, xin, xout, s, red, tol);
+    constexpr int NT = vc_threads<TX, TY>();
+    if (res) k_cycle2d_vc<TX, TY, true><<<nb, NT, 0, st>>>(g, f, xin, xout, s, red, tol);
+    else k_cycle2d_vc<TX, TY, false><<<nb, NT, 0, st>>>(g, f, xin, xout, s, red, tol);
     return hipGetLastError();
 }
 

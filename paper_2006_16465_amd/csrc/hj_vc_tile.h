@@ -36,19 +36,29 @@ __device__ __forceinline__ Face face_at(const GeomVC &g, int r, int q)
     return k;
 }
 
-// One cycle of tile `tile` by a workgroup of kNT threads (the three steps of
-// Sec. 4.1: tile + halo into LDS, nsub sub-iterations with the halo frozen,
-// owned points back).  Thread t owns column t % TX of the tile and rows
-// t / TX + j kNT / TX.  Returns this thread's share of ||r||^2 of xin over
-// the owned points (RES), else 0.  Several tiles in a row need a barrier
+// Threads per workgroup of the variable-coefficient cycle: every thread
+// holds the five face coefficients of each of its points in VGPRs, so tiles
+// of 1024 points and more take 512 threads (at most 8 points a thread).
+template <int TX, int TY>
+__host__ __device__ constexpr int vc_threads()
+{
+    return TX * TY >= 1024 ? 512 : kNT;
+}
+
+// One cycle of tile `tile` by a workgroup of NT = vc_threads threads (the
+// three steps of Sec. 4.1: tile + halo into LDS, nsub sub-iterations with the
+// halo frozen, owned points back).  Thread t owns column t % TX of the tile
+// and rows t / TX + j NT / TX.  Returns this thread's share of ||r||^2 of xin
+// over the owned points (RES), else 0.  Several tiles in a row need a barrier
 // between them (LDS is reused).
 template <int TX, int TY, bool RES>
 __device__ __forceinline__ double lds_tile_vc(const GeomVC &g, int tile, const double *__restrict__ f,
                                               const double *__restrict__ xin, double *__restrict__ xout,
                                               int nsub)
 {
-    static_assert(kNT % TX == 0 && (TX * TY) % kNT == 0, "tile/threads mismatch");
-    constexpr int P = TX + 2, R = TY + 2, PER = TX * TY / kNT, RSTEP = kNT / TX;
+    constexpr int NT = vc_threads<TX, TY>();
+    static_assert(NT % TX == 0 && (TX * TY) % NT == 0, "tile/threads mismatch");
+    constexpr int P = TX + 2, R = TY + 2, PER = TX * TY / NT, RSTEP = NT / TX;
     __shared__ double buf[2][R * P];
 
     const int bi = tile / g.ntx, bj = tile - bi * g.ntx;
@@ -58,7 +68,7 @@ __device__ __forceinline__ double lds_tile_vc(const GeomVC &g, int tile, const d
     const int ex = g.nx < TX ? g.nx : TX;
     const int64_t ld = g.ld;
 
-    for (int i = threadIdx.x; i < R * P; i += kNT) {
+    for (int i = threadIdx.x; i < R * P; i += NT) {
         const int lr = i / P, lc = i - lr * P;
         const int gr = r0 + lr - 1, gc = c0 + lc - 1;
         double v = 0.0;
