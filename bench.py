@@ -71,6 +71,26 @@ def cycle_kernel_name(tile, n):
     return f"k_cycle2d<double,{tx},{ty},true,true>"
 
 
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12  # 256 CUs x 128 B per clock x 2.4 GHz
+
+
+def cycle_lds_bytes_per_launch(n, tile, overlap, s, esize=8):
+    """LDS bytes one launch of the register-resident cycle moves: every sweep,
+    each thread writes the first and last rows of its C columns (its row
+    group's interface rows) and reads the two neighbouring groups' rows (the
+    frozen halo rows at the tile edge): 4 C values per thread and sweep.
+    None for the LDS ping-pong kernel."""
+    from paper_2006_16465_amd import hj
+    tx, ty = tile
+    if not cycle_kernel_name(tile, n).startswith("k_cycle2d_reg"):
+        return None
+    c = tx // 16
+    r = ty // 4 if (tx <= 64 and ty <= 32) else (8 if tx == 32 else 4)
+    threads = 64 * (ty // (4 * r))
+    tiles = hj.axis_tiles(n, tx, overlap[0]) * hj.axis_tiles(n, ty, overlap[1])
+    return tiles * threads * s * 4 * c * esize
+
+
 def kernel_source_hash():
     """Hash of the sources that define the cycle and sweep kernels."""
     h = hashlib.sha256()
@@ -206,6 +226,15 @@ def main():
         "avg_launch_us": round(avg_launch_s * 1e6, 2),
         "launches_per_step": launches,
     }
+    lds = cycle_lds_bytes_per_launch(n, tile, ov, s)
+    if lds is not None:
+        lds_tbs = lds / avg_launch_s / 1e12
+        roofline["lds"] = {"bytes_per_launch": lds, "achieved_tbs": round(lds_tbs, 2),
+                           "peak_tbs": round(LDS_PEAK_TBS, 2), "frac": round(lds_tbs / LDS_PEAK_TBS, 4)}
+    ntiles = hj.axis_tiles(n, tile[0], ov[0]) * hj.axis_tiles(n, tile[1], ov[1])
+    roofline["point_sweeps_per_s"] = {
+        "owned_g": round(n * n * s / avg_launch_s / 1e9, 1),
+        "computed_g": round(ntiles * min(tile[0], n) * min(tile[1], n) * s / avg_launch_s / 1e9, 1)}
 
     extra = {
         "cycles_per_seed": dict(zip(map(str, args.seeds), cycles_h)),

@@ -157,6 +157,15 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
     const int64_t ld = g.ld;
     const int lr0 = k * R, lc0 = j * C;
     const int64_t base = (int64_t)(r0 + lr0) * ld + c0 + lc0;
+    // LDS slot of the lane's column c in an interface row: columns go in
+    // 16-byte chunks, chunk q of all 16 lanes side by side, so each 16-byte
+    // LDS access of a row group covers 256 contiguous bytes (lane-strided
+    // chunks left half the banks idle on every access)
+    constexpr int E = 16 / (int)sizeof(T);
+    auto lcol = [j](int c) {
+        if constexpr (C >= E && C % E == 0) return ((c / E) * 16 + j) * E + c % E;
+        else return j * C + c;
+    };
 
     // step 1: tile, halo and f into registers / LDS (phase 0: row i in slot i)
     constexpr int NS = ROT ? R + 1 : R;
@@ -174,12 +183,12 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
     if (k == 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            s_halo[0][lc0 + c] = r0 > 0 ? xin[(int64_t)(r0 - 1) * ld + c0 + lc0 + c] : T(0);
+            s_halo[0][lcol(c)] = r0 > 0 ? xin[(int64_t)(r0 - 1) * ld + c0 + lc0 + c] : T(0);
     }
     if (k == NG - 1) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            s_halo[1][lc0 + c] =
+            s_halo[1][lcol(c)] =
                 r0 + TY < g.ny ? xin[(int64_t)(r0 + TY) * ld + c0 + lc0 + c] : T(0);
     }
     const int rlo = axis_own_begin(g.ny, TY, g.oy, bi) - r0 - lr0;
@@ -196,16 +205,16 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
     auto exchange = [&]<int P>(int par) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            s_top[par][k][lc0 + c] = x[P % NS][c];
-            s_bot[par][k][lc0 + c] = x[(R - 1 + P) % NS][c];
+            s_top[par][k][lcol(c)] = x[P % NS][c];
+            s_bot[par][k][lcol(c)] = x[(R - 1 + P) % NS][c];
         }
         __syncthreads();
-        const T *pu = k == 0 ? &s_halo[0][lc0] : &s_bot[par][k - 1][lc0];
-        const T *pd = k == NG - 1 ? &s_halo[1][lc0] : &s_top[par][k + 1][lc0];
+        const T *pu = k == 0 ? s_halo[0] : s_bot[par][k - 1];
+        const T *pd = k == NG - 1 ? s_halo[1] : s_top[par][k + 1];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            up[c] = pu[c];
-            dn[c] = pd[c];
+            up[c] = pu[lcol(c)];
+            dn[c] = pd[lcol(c)];
         }
     };
 
