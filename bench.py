@@ -142,6 +142,8 @@ def main():
     ap.add_argument("--no-diffusion", action="store_true",
                     help="skip the variable-coefficient / adjoint rows")
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D rows")
+    ap.add_argument("--no-replica", action="store_true",
+                    help="skip the rows on the paper's own experiment shapes (b = 1, x0 = 1, 1e-4)")
     ap.add_argument("--inner-tol", type=float, default=1e-6)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample budget")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -283,6 +285,8 @@ def main():
         extra["differentiable"] = diffusion_rows(torch, hj, stream)
     if not args.no_1d:
         extra["poisson1d"] = rows_1d(torch, hj, stream)
+    if not args.no_replica:
+        extra["paper_replicas"] = replica_rows(torch, hj, stream)
 
     cpu = None
     if not args.no_cpu:
@@ -487,6 +491,66 @@ def rows_1d(torch, hj, stream):
             cyc.append(info.cycles)
         out[name] = {"ms_per_problem": round(float(np.mean(ms)), 3), "cycles_per_seed": cyc}
     log(f"1d: {out}")
+    return out
+
+
+def replica_rows(torch, hj, stream):
+    """The paper's own experiment shapes (b = 1, x0 = 1, relative residual
+    1e-4): (R1) 1024 independent 1D systems of N = 1024 side by side, one
+    hj_solve_batched call each way, every step one launch over all copies;
+    (R2) one 2D 1024^2 system.  Global-memory Jacobi (1D: cycles with s = 1,
+    which are classical sweeps; 2D: the global sweep kernel) against the
+    paper's setting (32-point / 32x32 tiles, s = 16, no overlap) and an
+    overlapped shape (a cycle = s classical sweeps).  The paper's ~8x (1D)
+    and ~6x (2D) were measured on its own GPU: context, not a target."""
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3, r
+
+    out = {}
+    n, copies = 1024, 1024
+    h = 1.0 / (n + 1)
+    F = torch.ones(n, dtype=torch.float64, device="cuda")
+    xs = [torch.empty_like(F) for _ in range(copies)]
+    table = [(F, x, h) for x in xs]
+    r1 = {"workload": "1024 copies of 1D -u'' = 1, N = 1024, x0 = 1, to 1e-4 (one batched call)"}
+    for name, kw in (("global", dict(tile_1d=256, s_1d=1, overlap_1d=0)),
+                     ("paper_t32_s16", dict(tile_1d=32, s_1d=16, overlap_1d=0)),
+                     ("overlap_t256_s32_o62", dict(tile_1d=256, s_1d=32, overlap_1d=62))):
+        for x in xs:
+            x.fill_(1.0)
+        ms, infos = timed(lambda: hj.solve_batched(table, rel_tol=1e-4, max_cycles=1_000_000, **kw))
+        r1[name] = {"ms": round(ms, 1), "cycles": infos[0].cycles, "sweeps": infos[0].sweeps,
+                    "all_copies_same_cycles": all(i.cycles == infos[0].cycles for i in infos)}
+        log(f"replica R1 {name}: {ms:.1f} ms, {infos[0].cycles} cycles")
+    r1["speedup_paper_setting"] = round(r1["global"]["ms"] / r1["paper_t32_s16"]["ms"], 2)
+    r1["speedup_overlap"] = round(r1["global"]["ms"] / r1["overlap_t256_s32_o62"]["ms"], 2)
+    r1["hbm_pass_ratio_paper_setting"] = round(r1["global"]["cycles"] / r1["paper_t32_s16"]["cycles"], 2)
+    r1["note"] = ("every batched step is a cycle launch plus a judge launch over all copies, so the s = 1 "
+                  "steps of the global run pay the judge 128 760 times; the pass ratio is the paper's "
+                  "measure of work")
+    out["r1_1d_1024_copies"] = r1
+
+    F2 = torch.ones((n, n), dtype=torch.float64, device="cuda")
+    X2 = torch.empty_like(F2)
+    r2 = {"workload": "2D -lap u = 1 on 1024^2, x0 = 1, to 1e-4"}
+    tile2, s2, ov2, _ = hj.autotune(2, n, n)
+    for name, kw in (("global", dict(method="global")),
+                     ("paper_t32x32_s16", dict(tile=(32, 32), s=16, overlap=(0, 0))),
+                     ("overlap_autotuned", dict(tile=tile2, s=s2, overlap=ov2))):
+        X2.fill_(1.0)
+        ms, info = timed(lambda: hj.solve_2d(F2, X2, h, rel_tol=1e-4, max_cycles=1_000_000, **kw))
+        r2[name] = {"ms": round(ms, 1), "cycles": info.cycles, "sweeps": info.sweeps}
+        if name == "overlap_autotuned":
+            r2[name].update(tile=list(tile2), s=s2, overlap=list(ov2))
+        log(f"replica R2 {name}: {ms:.1f} ms, {info.cycles} cycles")
+    r2["speedup_paper_setting"] = round(r2["global"]["ms"] / r2["paper_t32x32_s16"]["ms"], 2)
+    r2["speedup_overlap"] = round(r2["global"]["ms"] / r2["overlap_autotuned"]["ms"], 2)
+    r2["hbm_pass_ratio_paper_setting"] = round(r2["global"]["cycles"] / r2["paper_t32x32_s16"]["cycles"], 2)
+    out["r2_2d_1024"] = r2
     return out
 
 

@@ -222,3 +222,26 @@ def test_refined_batch_cycle_cap_covers_all_phases():
             assert r <= 1.001e-10
         else:
             assert infos[i].rel_residual > 1e-10 and infos[i].cycles == cap
+
+
+@pytest.mark.parametrize("tile,s,ov,classical", [(32, 16, 0, False), (256, 32, 62, False), (256, 1, 0, True)])
+def test_paper_1d_experiment_shape_matches_oracle(orc, tile, s, ov, classical):
+    """The paper's 1D experiment shape: copies of -u'' = 1, N = 1024, x0 = 1,
+    solved side by side in one batch to 1e-4 (s = 1 cycles are classical
+    sweeps).  Every copy ends at the oracle's cycle count and iterate."""
+    n = 1024
+    h = 1.0 / (n + 1)
+    f, x0 = np.ones(n), np.ones(n)
+    if classical:
+        xo, co, relo, _ = orc.solve_1d(f, x0, h, method=orc.CLASSICAL, tol=1e-4)
+    else:
+        xo, co, relo, _ = orc.solve_1d(f, x0, h, tile=tile, s=s, overlap=ov, tol=1e-4)
+    F = dev(f)
+    xs = [dev(x0) for _ in range(8)]
+    infos = hj.solve_batched([(F, X, h) for X in xs], tile_1d=tile, s_1d=s, overlap_1d=ov, rel_tol=1e-4,
+                             max_cycles=1_000_000)
+    say(f"paper 1D shape tile={tile} s={s} ov={ov}: gpu cycles {infos[0].cycles}, oracle {co}")
+    for i, X in zip(infos, xs):
+        assert i.status == hj.HJ_OK and i.cycles == co
+        assert np.array_equal(host(X), xo)
+        assert abs(i.rel_residual - relo) <= 1e-9 * relo
