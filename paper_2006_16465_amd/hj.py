@@ -350,9 +350,13 @@ def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 1
     dtype, shape (n,) for 1D and (ny, nx) for 2D (row-major).  Each x is updated
     in place.  2D problems use the cycle (tile, s, overlap), 1D problems
     (tile_1d, s_1d, overlap_1d); autotune=True lets the library choose both.
-    refine=True (FP64 problems): FP64 cycles down to 1e4 * rel_tol, then FP32
-    correction cycles inside FP64 refinement (at most max_outer steps, 0 = 8).
-    Returns one Info per problem."""
+    refine=True (FP64 problems): each problem on its own schedule, FP64 cycles
+    down to min(1e4 rel_tol, rel_tol / 8F) (F its FP32 floor predicted from its
+    measured convergence rate), then FP32 correction cycles inside FP64
+    refinement (at most max_outer correction solves, 0 = 8; a problem whose
+    FP32 solve stops converging, or whose F is too large, continues in FP64).
+    max_cycles bounds every problem's cycles over all phases.  Info.cycles
+    counts the cycles inside each result.  Returns one Info per problem."""
     import torch
     if not problems:
         return []
