@@ -325,7 +325,11 @@ def mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream):
     the CPU oracle bit for bit (GPU tests); the refined solution's distance to
     it is reported per seed."""
     log(f"mixed precision: FP64 vs FP32 + FP64 refinement to {args.mixed_tol:g}")
-    out = {"tol": args.mixed_tol, "inner_tol": args.inner_tol, "fp64_ms": {}, "refined_ms": {},
+    exact = min(ov) >= 2 * s - 2
+    out = {"tol": args.mixed_tol, "inner_tol": args.inner_tol,
+           "switch_tol": (1e5 if exact else 1e4) * args.mixed_tol,
+           "switch_rule": "library default: 1e5 tol in the exact regime (overlap >= 2s - 2), else 1e4 tol",
+           "fp64_ms": {}, "refined_ms": {},
            "fp64_cycles": {}, "refined_fp64_cycles": {}, "refined_inner_cycles": {}, "refined_outer": {},
            "rel_diff_refined_vs_fp64": {}}
     x64 = torch.zeros_like(fs[0])

@@ -155,8 +155,10 @@ hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, 
  * smoothest and the most oscillatory), about 1e-6 times the residual at
  * which the FP32 phase starts; those modes then take as long to remove as
  * the slowest mode of the grid.  switch_tol keeps that residue below
- * rel_tol.  switch_tol = 0 selects min(1, 1e4 * rel_tol); switch_tol >= 1
- * runs FP32 from the start. */
+ * rel_tol.  switch_tol = 0 selects min(1, 1e4 * rel_tol), or min(1, 1e5 *
+ * rel_tol) in the exact regime (hierarchical, overlap >= 2s - 2 on both
+ * axes, where a cycle is s classical sweeps); switch_tol >= 1 runs FP32 from
+ * the start. */
 typedef struct hj_refine_params {
     hj_params inner;     /* cycle shape for both phases; FP32 solve tolerances (inner.rel_tol > 0) */
     double rel_tol;      /* > 0: outer tolerance on ||f - A x||_2 / ||f - A x_0||_2 */

@@ -266,9 +266,10 @@ def solve_2d_refined(f, x, h=None, *, hx=None, hy=None, tile=(64, 32), s=8, over
                      method="hierarchical", rel_tol=1e-10, inner_tol=1e-6, switch_tol=0.0,
                      inner_max_cycles=100_000, max_outer=50, check_every=0,
                      allow_not_converged=False) -> RefineInfo:
-    """FP64 solve: FP64 cycles down to switch_tol (0 = 1e4 * rel_tol), then FP32
-    cycles inside FP64 iterative refinement (hj_solve_2d_refined).  f and x are
-    FP64 (ny, nx) tensors; x is updated in place."""
+    """FP64 solve: FP64 cycles down to switch_tol (0 = 1e4 * rel_tol, or
+    1e5 * rel_tol when overlap >= 2s - 2 on both axes), then FP32 cycles inside
+    FP64 iterative refinement (hj_solve_2d_refined).  f and x are FP64 (ny, nx)
+    tensors; x is updated in place."""
     import torch
     _check_pair(f, x)
     if f.dtype != torch.float64:
