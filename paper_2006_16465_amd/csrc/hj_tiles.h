@@ -167,7 +167,12 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
         else return j * C + c;
     };
 
-    // step 1: tile, halo and f into registers / LDS (phase 0: row i in slot i)
+    // step 1: tile, halo and f into registers / LDS (phase 0: row i in slot i).
+    // The loads issue at raised wave priority, the sweeps at the base one:
+    // the workgroup that is loading gets its memory instructions out ahead
+    // of the sweeping workgroup's VALU work on the same SIMDs, so the two
+    // phases overlap better (4 % per 4096^2 cycle, measured A/B).
+    __builtin_amdgcn_s_setprio(3);
     constexpr int NS = ROT ? R + 1 : R;
     T x[NS][C], bq[R][C], hw[R], he[R];
 #pragma unroll
@@ -191,6 +196,7 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
             s_halo[1][lcol(c)] =
                 r0 + TY < g.ny ? xin[(int64_t)(r0 + TY) * ld + c0 + lc0 + c] : T(0);
     }
+    __builtin_amdgcn_s_setprio(0);
     const int rlo = axis_own_begin(g.ny, TY, g.oy, bi) - r0 - lr0;
     const int rhi = axis_own_end(g.ny, TY, g.oy, bi, g.nty) - r0 - lr0;
     const int clo = axis_own_begin(g.nx, TX, g.ox, bj) - c0 - lc0;
