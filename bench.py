@@ -468,8 +468,10 @@ def batched_rows(args, torch, hj, stream):
 def rows_1d(torch, hj, stream):
     """1D Poisson, N = 256 interior points, 8 random sine modes (seeds 0-4),
     x0 = 0, to 1e-6: the paper's setting (32-point tiles, s = 16, no overlap),
-    64-point tiles with s = 8 and overlap 14 (a cycle = 8 classical sweeps),
-    and global-memory Jacobi.  Mean ms per problem (median of 5 repeats)."""
+    64-point tiles with s = 8 and overlap 14 (a cycle = 8 classical sweeps;
+    the five tiles fit one workgroup, which runs every cycle in one launch),
+    the same shape with one launch per cycle, and global-memory Jacobi.  Mean
+    ms per problem (median of 5 repeats)."""
     from paper_2006_16465_amd import workloads as W
     n = 256
     h = W.grid_h(n)
@@ -478,6 +480,7 @@ def rows_1d(torch, hj, stream):
     out = {"workload": "poisson1d_n256: -u'' = f, N = 256, f = 8 random sine modes (seeds 0-4), x0 = 0, to 1e-6"}
     for name, kw in (("paper_t32_s16", dict(tile=32, s=16, overlap=0)),
                      ("overlap_t64_s8_o14", dict(tile=64, s=8, overlap=14)),
+                     ("overlap_t64_s8_o14_launch_per_cycle", dict(tile=64, s=8, overlap=14, launch_per_cycle=True)),
                      ("global", dict(method="global"))):
         ms, cyc = [], []
         for f in fs:

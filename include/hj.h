@@ -90,6 +90,13 @@ typedef enum hj_method { HJ_HIERARCHICAL = 0, HJ_GLOBAL = 1 } hj_method;
 /* hj_params.flags: run every 2D cycle on the LDS ping-pong kernel instead of
  * the register-resident one (same iterates; for comparison and testing). */
 #define HJ_FLAG_LDS_KERNEL 0x1
+/* hj_params.flags, 1D hierarchical solves: one kernel launch per cycle even
+ * where one workgroup can run the whole solve (same iterates; for comparison
+ * and testing).  Without it, a 1D hierarchical solve with tiles of 64, 128,
+ * 256 or 512 points, at most 16 tiles and 3 n element sizes of at most
+ * 60 KiB runs all its cycles inside one workgroup (Sec. 3.3 cycle, global
+ * iterates in LDS, the residual judged on the device every cycle). */
+#define HJ_FLAG_LAUNCH_PER_CYCLE 0x2
 
 typedef struct hj_params {
     int32_t tile_x;      /* interior tile extent along x (1D: the tile); 0 = 32.
@@ -105,7 +112,7 @@ typedef struct hj_params {
     int32_t check_every; /* cycles enqueued between host polls of the device-side
                             convergence flag; 0 = adaptive (about 0.5 ms of GPU work
                             per poll).  Does not change results. */
-    int32_t flags;       /* 0, or HJ_FLAG_LDS_KERNEL */
+    int32_t flags;       /* 0, or HJ_FLAG_LDS_KERNEL | HJ_FLAG_LAUNCH_PER_CYCLE */
     double rel_tol;      /* > 0: stop at the first cycle c with ||r_c|| <= rel_tol ||r_0||.
                             <= 0: run exactly max_cycles cycles with no residual
                             evaluation in between (fixed-count mode). */

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhj.so")
-SOURCES = ["hj_api.hip", "hj_kernels.hip", "hj_refine.hip", "hj_vc.hip", "hj_batch.hip"]
+SOURCES = ["hj_api.hip", "hj_kernels.hip", "hj_refine.hip", "hj_vc.hip", "hj_batch.hip", "hj_solve1d_wg.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -112,7 +112,8 @@ hj_status check_ptr_dtype(const void *p, hj_dtype dt, const char *name, bool may
 hj_status check_params(const hj_params *p, int dim)
 {
     if (!p) return fail(HJ_ERR_INVALID_ARG, "params is NULL");
-    if (p->flags & ~HJ_FLAG_LDS_KERNEL) return fail(HJ_ERR_INVALID_ARG, "unknown bits in params.flags");
+    if (p->flags & ~(HJ_FLAG_LDS_KERNEL | HJ_FLAG_LAUNCH_PER_CYCLE))
+        return fail(HJ_ERR_INVALID_ARG, "unknown bits in params.flags");
     if (p->method != HJ_HIERARCHICAL && p->method != HJ_GLOBAL)
         return fail(HJ_ERR_INVALID_ARG, "params.method must be HJ_HIERARCHICAL or HJ_GLOBAL");
     if (p->max_cycles < 1) return fail(HJ_ERR_INVALID_ARG, "params.max_cycles must be >= 1");
@@ -1061,6 +1062,44 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
     return status;
 }
 
+// The whole 1D solve in one workgroup: cycles run in chunks of kWgChunk per
+// launch (a few ms of GPU time), the solve state carried in S.ctrl.  Same stop
+// rule, iterates and info as drive().
+constexpr int64_t kWgChunk = 4096;
+
+hj_status drive_1d_wg(const hj::Geom1 &g, int dt, const hj_params &p, const void *f, void *x, hipStream_t st,
+                      DevScratch &S, hj_info *info)
+{
+    const int64_t maxc = p.max_cycles;
+    const bool every = p.rel_tol > 0.0;
+    const double tol = every ? p.rel_tol : -1.0;
+    hj_status r;
+    hj::Ctrl c{};
+    HJ_HIP(hj::launch_ctrl_init(S.ctrl, st));
+    for (int64_t cb = 0;;) {
+        const int64_t ce = maxc - cb < kWgChunk ? maxc + 1 : cb + kWgChunk;
+        HJ_HIP(hj::launch_solve1d_wg(dt, g, p.s, f, x, cb, ce, maxc, tol, every, S.ctrl, st));
+        if (ce == maxc + 1) break;
+        if (every) {
+            if ((r = read_ctrl(S, st, c)) != HJ_OK) return r;
+            if (c.status != hj::ST_RUNNING) break;
+        }
+        cb = ce;
+    }
+    if ((r = read_ctrl(S, st, c)) != HJ_OK) return r;
+    const int64_t final_c = every && c.status != hj::ST_RUNNING ? c.done_cycle : maxc;
+    if (info) {
+        info->cycles = final_c;
+        info->sweeps = final_c * p.s;
+        info->r0_norm = std::sqrt(c.r0sq);
+        info->rel_residual = c.r0sq > 0.0 ? std::sqrt(c.last_rsq) / std::sqrt(c.r0sq) : 0.0;
+        if (!std::isfinite(c.last_rsq)) info->rel_residual = NAN;
+    }
+    if (c.status == hj::ST_NONFINITE) return fail(HJ_ERR_NONFINITE, "residual norm became non-finite");
+    if (every && c.status != hj::ST_CONVERGED) return fail(HJ_ERR_NOT_CONVERGED, "max_cycles reached before rel_tol");
+    return HJ_OK;
+}
+
 hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *x,
                       const hj_params *p, void *stream, hj_info *info)
 {
@@ -1086,12 +1125,16 @@ hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *
     const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
     const size_t es = esize(dtype);
     const bool hier = P.method == HJ_HIERARCHICAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (hier && !(P.flags & HJ_FLAG_LAUNCH_PER_CYCLE) && hj::solve1d_wg_supported(g, dt)) {
+        if ((r = scratch_ensure(S, 0, 0)) != HJ_OK) return r;
+        return drive_1d_wg(g, dt, P, f, x, st, S, info);
+    }
     const int64_t nbc = hier ? hj::cycle1d_blocks(g) : hj::sweep1d_blocks(g);
     const int64_t nbr = hj::resid1d_blocks(g);
     if (nbc > INT32_MAX || nbr > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "grid too large");
     const size_t xbytes = (size_t)n * es;
     if ((r = scratch_ensure(S, 2 * xbytes, 2 * std::max(nbc, nbr))) != HJ_OK) return r;
-    hipStream_t st = (hipStream_t)stream;
 
     Step step;
     step.nb_cycle = (int)nbc;

@@ -63,6 +63,15 @@ hipError_t launch_sweep1d(int dt, const Geom1 &g, bool res, const void *f, const
 hipError_t launch_resid1d(int dt, const Geom1 &g, const void *f, const void *x, void *r_out,
                           double *part, hipStream_t st);
 
+// Whole 1D hierarchical solve in one workgroup (register tiles of 64..512
+// points, at most 16 tiles, f and two iterates in LDS).  Runs cycles
+// [c_begin, c_end) (c_end <= maxc + 1) on x in place, carrying the solve state
+// in ctrl from one launch to the next; every: judge every iterate (tolerance
+// mode), else only iterates 0 and maxc.
+bool solve1d_wg_supported(const Geom1 &g, int dt);
+hipError_t launch_solve1d_wg(int dt, const Geom1 &g, int s, const void *f, void *x, int64_t c_begin,
+                             int64_t c_end, int64_t maxc, double tol, bool every, Ctrl *ctrl, hipStream_t st);
+
 // Sum n partials and judge iterate c (one workgroup).
 hipError_t launch_judge(const double *part, int n, Ctrl *ctrl, int64_t c, double tol, hipStream_t st);
 

@@ -1,0 +1,165 @@
+// hj_solve1d_wg.hip -- a whole 1D hierarchical solve inside one workgroup.
+//
+// When every tile of a 1D problem fits in one workgroup (at most 16 register
+// tiles, one per wavefront) and the grid fits in LDS, a cycle needs no kernel
+// launch of its own.  The two global iterates and f sit in LDS; each
+// wavefront runs its tile's cycle in registers with the same body as the
+// per-cycle kernel (load with a frozen halo, s sweeps, write-back of the owned
+// points: Sec. 3.3, with the overlap of Sec. 3.5); the workgroup barrier that
+// ends the cycle is the global synchronisation between cycles.  The residual
+// of the iterate a cycle reads is reduced in the same pass and judged at once,
+// so the solve stops at the same iterate as the per-cycle path, and the
+// iterates agree with it bit for bit.  At the paper's 1D size (256 points) a
+// cycle then costs a few hundred nanoseconds instead of a launch.
+#include "hj_launch.h"
+#include "hj_tiles.h"
+
+namespace hj {
+namespace {
+
+constexpr int kWgThreads = 1024;              // 16 wavefronts
+constexpr int kWgMaxTiles = kWgThreads / 64;  // one tile per wavefront
+constexpr size_t kWgMaxLds = 60 * 1024;       // f and the two iterates
+
+// v from lane CTRL selects, 0 in rows ROW_MASK leaves out.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_or_zero(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront (all lanes active), in every lane:
+// quads, half rows and rows of 16 by lane permutations, then rows 0+1 and
+// 2+3 by broadcasts of lane 15 of a row into the next, and the total in lane
+// 63 read back as a uniform value.
+__device__ __forceinline__ double wave_total(double v)
+{
+    v += dpp_or_zero<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_or_zero<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_or_zero<0x141, 0xf>(v);  // row_half_mirror
+    v += dpp_or_zero<0x140, 0xf>(v);  // row_mirror
+    v += dpp_or_zero<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_or_zero<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Cycles [c_begin, c_end) of the solve; c_end <= maxc + 1.  The pass for
+// c == maxc runs no sweep (it only evaluates the residual of iterate maxc).
+// x holds iterate c_begin on entry and, on return, the iterate the solve
+// stopped at (tolerance mode) or iterate c_end (c_end <= maxc) / maxc.
+// every: judge every iterate (tolerance mode), else only iterates 0 and maxc.
+template <typename T, int TT>
+__global__ __launch_bounds__(kWgThreads) void k_solve1d_wg(Geom1 g, const T *__restrict__ f, T *__restrict__ x,
+                                                           int s, int64_t c_begin, int64_t c_end, int64_t maxc,
+                                                           double tol, int every, Ctrl *ctrl)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2][kWgThreads / 64];  // wavefront sums, by cycle parity
+    const int n = (int)g.n;
+    T *fl = (T *)smem;
+    T *b0 = fl + n;
+    T *b1 = b0 + n;
+    for (int i = (int)threadIdx.x; i < n; i += kWgThreads) {
+        fl[i] = f[i];
+        b0[i] = x[i];
+    }
+    // Solve state, identical in every thread (read before any thread of this
+    // launch writes the block: the writes below follow several barriers).
+    int32_t status = ctrl->status;
+    double r0sq = ctrl->r0sq, last = ctrl->last_rsq;
+    int64_t done = ctrl->done_cycle;
+    __syncthreads();
+
+    int64_t c = c_begin;
+    bool stop = false;
+    for (; c < c_end; ++c) {
+        const bool odd = ((c - c_begin) & 1) != 0;
+        const T *xin = odd ? b1 : b0;
+        T *xout = odd ? b0 : b1;
+        const double mine = reg_tiles_1d<T, TT, true>(g, 0, fl, xin, xout, c < maxc ? s : 0);
+        const double wsum = wave_total(mine);
+        if ((threadIdx.x & 63) == 0) red[odd][threadIdx.x >> 6] = wsum;
+        // The one barrier of a cycle: every write-back (and wavefront sum) of
+        // this cycle is visible after it, and every read of xin is done before
+        // the next cycle overwrites it.  red alternates with the cycle parity,
+        // so the next cycle's sums land in the other half while slow
+        // wavefronts still read this one.
+        __syncthreads();
+        double tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWgThreads / 64; ++w) tot += red[odd][w];
+        if (status == ST_RUNNING && (every || c == 0 || c == maxc)) {
+            if (c == 0) r0sq = tot;
+            last = tot;
+            const double rel = r0sq > 0.0 ? sqrt(tot) / sqrt(r0sq) : 0.0;
+            if (!isfinite(tot)) status = ST_NONFINITE;
+            else if (rel <= tol) status = ST_CONVERGED;
+            if (status != ST_RUNNING) done = c;
+        }
+        if (every && status != ST_RUNNING) {
+            stop = true;
+            break;
+        }
+    }
+    // Iterate k sits in buffer (k - c_begin) & 1; after the pass for maxc
+    // both buffers hold iterate maxc.
+    const int64_t k = stop ? c : c_end;
+    const T *res = ((k - c_begin) & 1) ? b1 : b0;
+    for (int i = (int)threadIdx.x; i < n; i += kWgThreads) x[i] = res[i];
+    if (threadIdx.x == 0) {
+        ctrl->r0sq = r0sq;
+        ctrl->last_rsq = last;
+        ctrl->iter = k;
+        ctrl->done_cycle = done;
+        ctrl->status = status;
+    }
+}
+
+template <typename T>
+hipError_t launch_t(const Geom1 &g, int s, const void *f, void *x, int64_t c_begin, int64_t c_end, int64_t maxc,
+                    double tol, bool every, Ctrl *ctrl, hipStream_t st)
+{
+    const size_t lds = 3 * (size_t)g.n * sizeof(T);
+    const int ev = every ? 1 : 0;
+#define HJ_WG(TT)                                                                                            \
+    case TT:                                                                                                 \
+        k_solve1d_wg<T, TT><<<1, kWgThreads, lds, st>>>(g, (const T *)f, (T *)x, s, c_begin, c_end, maxc, tol, \
+                                                        ev, ctrl);                                           \
+        break;
+    switch (g.t) {
+        HJ_WG(64)
+        HJ_WG(128)
+        HJ_WG(256)
+        HJ_WG(512)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef HJ_WG
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool solve1d_wg_supported(const Geom1 &g, int dt)
+{
+    const size_t es = dt == F64 ? sizeof(double) : sizeof(float);
+    const bool tile = g.t == 64 || g.t == 128 || g.t == 256 || g.t == 512;
+    return tile && g.nt >= 1 && g.nt <= kWgMaxTiles && 3 * (size_t)g.n * es <= kWgMaxLds;
+}
+
+hipError_t launch_solve1d_wg(int dt, const Geom1 &g, int s, const void *f, void *x, int64_t c_begin,
+                             int64_t c_end, int64_t maxc, double tol, bool every, Ctrl *ctrl, hipStream_t st)
+{
+    if (!solve1d_wg_supported(g, dt) || c_begin < 0 || c_end <= c_begin || c_end > maxc + 1 || s < 1)
+        return hipErrorInvalidValue;
+    if (dt == F64) return launch_t<double>(g, s, f, x, c_begin, c_end, maxc, tol, every, ctrl, st);
+    return launch_t<float>(g, s, f, x, c_begin, c_end, maxc, tol, every, ctrl, st);
+}
+
+}  // namespace hj

@@ -23,6 +23,7 @@ HJ_OK, HJ_ERR_INVALID_ARG, HJ_ERR_NOT_CONVERGED, HJ_ERR_NONFINITE, HJ_ERR_UNSUPP
 HJ_F64, HJ_F32 = 0, 1
 HJ_HIERARCHICAL, HJ_GLOBAL = 0, 1
 HJ_FLAG_LDS_KERNEL = 0x1
+HJ_FLAG_LAUNCH_PER_CYCLE = 0x2
 METHODS = {"hierarchical": HJ_HIERARCHICAL, "global": HJ_GLOBAL}
 
 
@@ -179,7 +180,7 @@ def axis_tiles(n: int, tile: int, overlap: int = 0) -> int:
 
 
 def make_params(tile=32, s=16, method="hierarchical", rel_tol=1e-6, max_cycles=1_000_000,
-                check_every=0, overlap=0, lds_kernel=False) -> Params:
+                check_every=0, overlap=0, lds_kernel=False, launch_per_cycle=False) -> Params:
     p = Params()
     load().hj_params_default(ctypes.byref(p))
     tx, ty = (tile, tile) if isinstance(tile, int) else tile
@@ -190,7 +191,7 @@ def make_params(tile=32, s=16, method="hierarchical", rel_tol=1e-6, max_cycles=1
     p.rel_tol = rel_tol
     p.max_cycles = max_cycles
     p.check_every = check_every
-    p.flags = HJ_FLAG_LDS_KERNEL if lds_kernel else 0
+    p.flags = (HJ_FLAG_LDS_KERNEL if lds_kernel else 0) | (HJ_FLAG_LAUNCH_PER_CYCLE if launch_per_cycle else 0)
     return p
 
 
@@ -229,12 +230,16 @@ def _raise_or_info(st: int, info: _Info, allow_not_converged: bool) -> Info:
 
 
 def solve_1d(f, x, h, *, tile=32, s=16, method="hierarchical", rel_tol=1e-6, max_cycles=1_000_000,
-             check_every=0, overlap=0, allow_not_converged=False) -> Info:
-    """Solve -u'' = f (n interior points, spacing h) in place in x (hj_solve_1d)."""
+             check_every=0, overlap=0, allow_not_converged=False, launch_per_cycle=False) -> Info:
+    """Solve -u'' = f (n interior points, spacing h) in place in x (hj_solve_1d).
+    Small hierarchical solves (tiles of 64-512 points, at most 16 tiles, f and
+    two iterates within 60 KiB) run all their cycles in one workgroup;
+    launch_per_cycle=True forces one kernel launch per cycle (same iterates)."""
     _check_pair(f, x)
     if f.dim() != 1 or not f.is_contiguous() or not x.is_contiguous():
         raise ValueError("1D tensors must be contiguous vectors")
-    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap)
+    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap,
+                    launch_per_cycle=launch_per_cycle)
     info = _Info()
     with _device(f):
         st = load().hj_solve_1d(f.numel(), float(h), _dtype_code(f), f.data_ptr(), x.data_ptr(),

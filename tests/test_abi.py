@@ -56,7 +56,7 @@ FAKE = 0x10000  # aligned non-NULL pointer; validation must reject before it is 
     ((8, 8, 8, 0.1, 0.1, 0), {"overlap_x": 32}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"overlap_y": -2}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"method": 5}, hj.HJ_ERR_INVALID_ARG),
-    ((8, 8, 8, 0.1, 0.1, 0), {"flags": 2}, hj.HJ_ERR_INVALID_ARG),
+    ((8, 8, 8, 0.1, 0.1, 0), {"flags": 4}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"rel_tol": float("nan")}, hj.HJ_ERR_INVALID_ARG),
     ((8, 8, 8, 0.1, 0.1, 0), {"tile_x": 48}, hj.HJ_ERR_UNSUPPORTED),
     ((8, 8, 8, 0.1, 0.1, 0), {"tile_x": 16, "tile_y": 128}, hj.HJ_ERR_UNSUPPORTED),
