@@ -56,17 +56,6 @@ namespace {
 constexpr double kU32 = 5.9604644775390625e-08;  // 2^-24, FP32 unit roundoff
 constexpr double kLn2 = 0.6931471805599453;
 
-template <typename T>
-struct Prec;
-template <>
-struct Prec<double> {
-    static constexpr int id = F64;
-};
-template <>
-struct Prec<float> {
-    static constexpr int id = F32;
-};
-
 template <int NT>
 __device__ __forceinline__ void post_partial_at(double mine, double *slot)
 {

@@ -86,6 +86,12 @@ def test_solve_rejects_null_and_misaligned_pointers():
     assert lib.hj_solve_1d(16, -1.0, 0, FAKE, FAKE, ctypes.byref(p), None, ctypes.byref(info)) == 1
     p1 = _params(tile_x=48)
     assert lib.hj_solve_1d(16, 0.1, 0, FAKE, FAKE, ctypes.byref(p1), None, ctypes.byref(info)) == hj.HJ_ERR_UNSUPPORTED
+    # flags: HJ_FLAG_LAUNCH_PER_CYCLE passes validation (the call then needs a
+    # device); an unknown bit does not
+    pf = _params(tile_x=64, flags=hj.HJ_FLAG_LAUNCH_PER_CYCLE)
+    assert lib.hj_solve_1d(16, 0.1, 0, FAKE, FAKE, ctypes.byref(pf), None, ctypes.byref(info)) != 1
+    pf = _params(tile_x=64, flags=8)
+    assert lib.hj_solve_1d(16, 0.1, 0, FAKE, FAKE, ctypes.byref(pf), None, ctypes.byref(info)) == 1
     nrm = ctypes.c_double()
     assert lib.hj_residual(3, 8, 8, 8, 0.1, 0.1, 0, FAKE, FAKE, None, ctypes.byref(nrm), None) == 1
     assert lib.hj_residual(2, 8, 8, 4, 0.1, 0.1, 0, FAKE, FAKE, None, ctypes.byref(nrm), None) == 1
