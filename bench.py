@@ -527,21 +527,29 @@ def replica_rows(torch, hj, stream):
     for name, kw in (("global", dict(tile_1d=256, s_1d=1, overlap_1d=0)),
                      ("paper_t32_s16", dict(tile_1d=32, s_1d=16, overlap_1d=0)),
                      ("paper_t32_s16_o4", dict(tile_1d=32, s_1d=16, overlap_1d=4)),
-                     ("overlap_t256_s32_o62", dict(tile_1d=256, s_1d=32, overlap_1d=62))):
+                     ("overlap_t256_s32_o62", dict(tile_1d=256, s_1d=32, overlap_1d=62)),
+                     ("overlap_t256_s32_o62_one_workgroup",
+                      dict(tile_1d=256, s_1d=32, overlap_1d=62, one_workgroup_1d=True))):
         for x in xs:
             x.fill_(1.0)
         ms, infos = timed(lambda: hj.solve_batched(table, rel_tol=1e-4, max_cycles=1_000_000, **kw))
         r1[name] = {"ms": round(ms, 1), "cycles": infos[0].cycles, "sweeps": infos[0].sweeps,
                     "all_copies_same_cycles": all(i.cycles == infos[0].cycles for i in infos)}
+        if name == "overlap_t256_s32_o62":
+            x_steps = xs[0].clone()
+        elif name.endswith("one_workgroup"):
+            r1[name]["iterate_equals_per_step_run"] = bool(torch.equal(xs[0], x_steps))
         log(f"replica R1 {name}: {ms:.1f} ms, {infos[0].cycles} cycles")
     r1["speedup_paper_setting"] = round(r1["global"]["ms"] / r1["paper_t32_s16"]["ms"], 2)
     r1["speedup_paper_overlap_setting"] = round(r1["global"]["ms"] / r1["paper_t32_s16_o4"]["ms"], 2)
     r1["paper_reported"] = {"t32_s16": 3.79, "t32_s16_o4": 8.00, "note": "the paper's Tables 1 and 2, its own GPU"}
     r1["speedup_overlap"] = round(r1["global"]["ms"] / r1["overlap_t256_s32_o62"]["ms"], 2)
+    r1["speedup_overlap_one_workgroup"] = round(r1["global"]["ms"] / r1["overlap_t256_s32_o62_one_workgroup"]["ms"], 2)
     r1["hbm_pass_ratio_paper_setting"] = round(r1["global"]["cycles"] / r1["paper_t32_s16"]["cycles"], 2)
     r1["note"] = ("every batched step is a cycle launch plus a judge launch over all copies, so the s = 1 "
                   "steps of the global run pay the judge 128 760 times; the pass ratio is the paper's "
-                  "measure of work")
+                  "measure of work.  The one-workgroup row runs each copy's whole solve inside one "
+                  "workgroup (HJ_BATCH_WG1D): one launch, iterates in LDS")
     out["r1_1d_1024_copies"] = r1
 
     F2 = torch.ones((n, n), dtype=torch.float64, device="cuda")

@@ -212,6 +212,14 @@ typedef struct hj_problem {
 
 #define HJ_BATCH_AUTOTUNE 0x1
 #define HJ_BATCH_REFINE 0x2
+/* 1D problems only, each solved inside one workgroup: one launch covers
+ * every problem's cycles (in launches of up to 4096 cycles), the iterates and
+ * f in LDS, as hj_solve_1d runs a small grid.  Needs p1 hierarchical with
+ * tile_x in {64, 128, 256, 512} and every problem at most 16 tiles with 3 n
+ * element sizes of at most 60 KiB; not with HJ_BATCH_AUTOTUNE or
+ * HJ_BATCH_REFINE (HJ_ERR_UNSUPPORTED otherwise).  Iterates, cycle counts
+ * and infos are those of each problem's own hj_solve_1d call. */
+#define HJ_BATCH_WG1D 0x4
 
 typedef struct hj_batch_params {
     hj_params p2;         /* 2D cycle: tile_x in {32, 64}, tile_y in {16, 32, 64, 128},
@@ -223,7 +231,8 @@ typedef struct hj_batch_params {
                              of all phases together) */
     int32_t dtype;        /* hj_dtype of every f and x */
     int32_t graph_cycles; /* cycles per graph replay, 0 = 8, at most 1024 */
-    int32_t flags;        /* HJ_BATCH_AUTOTUNE: choose p2 and p1 with hj_autotune (2D on the
+    int32_t flags;        /* HJ_BATCH_WG1D: see above.
+                             HJ_BATCH_AUTOTUNE: choose p2 and p1 with hj_autotune (2D on the
                              largest 2D problem, tiles limited to the smallest);
                              HJ_BATCH_REFINE: FP64 problems (dtype HJ_F64, rel_tol > 0), each on
                              its own schedule: FP64 cycles down to min(1e4 rel_tol,

@@ -407,6 +407,8 @@ struct BatchScratch {
     int64_t nstate = 0;
     hj::BState *host = nullptr;  // 2 x nhost pinned
     int64_t nhost = 0;
+    void *wg = nullptr;  // one-workgroup 1D batches: problem table and states
+    size_t wg_bytes = 0;
 };
 
 BatchScratch g_bat[kMaxDev];
@@ -1254,6 +1256,94 @@ hj_status hj_autotune_batch(const hj_problem *probs, int64_t nprob, hj_dtype dty
     return HJ_OK;
 }
 
+// HJ_BATCH_WG1D: workgroup i runs problem i's whole solve (the one-workgroup
+// body of hj_solve_1d); cycles in launches of kWgChunk, the per-problem
+// states read back between launches in tolerance mode.  Called with the
+// device's scratch lock held, problems already checked.
+hj_status solve_batched_wg1d(const hj_problem *probs, int64_t nprob, const hj_batch_params &p, hj_dtype dtype,
+                             hipStream_t st, BatchScratch &B, hj_info *infos)
+{
+    const hj_params &P1 = p.p1;
+    const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
+    std::vector<hj::WgProb> table((size_t)nprob);
+    int64_t max_n = 0, max_nt = 0;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const hj_problem &q = probs[i];
+        if (q.dim != 1) return fail(HJ_ERR_UNSUPPORTED, "HJ_BATCH_WG1D takes 1D problems only");
+        const hj::Geom1 g = make_geom1(q.nx, q.hx, &P1);
+        if (!hj::solve1d_wg_supported(g, dt))
+            return fail(HJ_ERR_UNSUPPORTED, "problem " + std::to_string(i) +
+                                                ": HJ_BATCH_WG1D needs tiles of 64..512 points, at most 16 tiles "
+                                                "and 3 n element sizes of at most 60 KiB");
+        table[(size_t)i] = hj::WgProb{g, q.f, q.x};
+        max_n = std::max(max_n, g.n);
+        max_nt = std::max(max_nt, g.nt);
+    }
+    const size_t tbytes = ((size_t)nprob * sizeof(hj::WgProb) + 255) / 256 * 256;
+    const size_t need = tbytes + (size_t)nprob * sizeof(hj::Ctrl);
+    if (need > B.wg_bytes) {
+        if (B.wg) HJ_HIP(hipFree(B.wg));
+        B.wg = nullptr;
+        B.wg_bytes = 0;
+        HJ_HIP(hipMalloc(&B.wg, need));
+        B.wg_bytes = need;
+    }
+    hj::WgProb *dprobs = (hj::WgProb *)B.wg;
+    hj::Ctrl *ctrls = (hj::Ctrl *)((char *)B.wg + tbytes);
+    HJ_HIP(hipMemcpyAsync(dprobs, table.data(), (size_t)nprob * sizeof(hj::WgProb), hipMemcpyHostToDevice, st));
+    HJ_HIP(hj::launch_ctrl_init_n(ctrls, nprob, st));
+
+    const int64_t maxc = p.max_cycles;
+    const bool every = p.rel_tol > 0.0;
+    const double tol = every ? p.rel_tol : -1.0;
+    std::vector<hj::Ctrl> hc((size_t)nprob);
+    auto read_back = [&]() -> hj_status {
+        HJ_HIP(hipMemcpyAsync(hc.data(), ctrls, (size_t)nprob * sizeof(hj::Ctrl), hipMemcpyDeviceToHost, st));
+        HJ_HIP(hipStreamSynchronize(st));
+        return HJ_OK;
+    };
+    hj_status r;
+    for (int64_t cb = 0;;) {
+        const int64_t ce = maxc - cb < kWgChunk ? maxc + 1 : cb + kWgChunk;
+        HJ_HIP(hj::launch_solve1d_wg_batch(dt, P1.tile_x, dprobs, nprob, max_n, max_nt, P1.s, cb, ce, maxc, tol,
+                                           every, ctrls, st));
+        if (ce == maxc + 1) break;
+        if (every) {
+            if ((r = read_back()) != HJ_OK) return r;
+            if (std::none_of(hc.begin(), hc.end(), [](const hj::Ctrl &c) { return c.status == hj::ST_RUNNING; }))
+                break;
+        }
+        cb = ce;
+    }
+    if ((r = read_back()) != HJ_OK) return r;
+
+    hj_status status = HJ_OK;
+    int64_t bad = -1;
+    for (int64_t i = 0; i < nprob; ++i) {
+        const hj::Ctrl &c = hc[(size_t)i];
+        const int64_t used = every && c.status != hj::ST_RUNNING ? c.done_cycle : maxc;
+        if (infos) {
+            infos[i].cycles = used;
+            infos[i].sweeps = used * P1.s;
+            infos[i].r0_norm = std::sqrt(c.r0sq);
+            infos[i].rel_residual = c.r0sq > 0.0 ? std::sqrt(c.last_rsq) / std::sqrt(c.r0sq) : 0.0;
+            if (!std::isfinite(c.last_rsq)) infos[i].rel_residual = NAN;
+        }
+        if (c.status == hj::ST_NONFINITE) {
+            status = HJ_ERR_NONFINITE;
+            bad = i;
+        } else if (c.status != hj::ST_CONVERGED && every && status == HJ_OK) {
+            status = HJ_ERR_NOT_CONVERGED;
+            bad = i;
+        }
+    }
+    if (status == HJ_ERR_NONFINITE)
+        return fail(status, "problem " + std::to_string(bad) + ": residual norm became non-finite");
+    if (status == HJ_ERR_NOT_CONVERGED)
+        return fail(status, "problem " + std::to_string(bad) + " did not reach rel_tol within max_cycles");
+    return HJ_OK;
+}
+
 hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batch_params *p,
                            void *stream, hj_info *infos)
 {
@@ -1267,9 +1357,13 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
     if (p->max_cycles < 1) return fail(HJ_ERR_INVALID_ARG, "max_cycles must be >= 1");
     if (p->graph_cycles < 0 || p->graph_cycles > 1024)
         return fail(HJ_ERR_INVALID_ARG, "graph_cycles must be in [0, 1024]");
-    if (p->flags & ~(HJ_BATCH_AUTOTUNE | HJ_BATCH_REFINE)) return fail(HJ_ERR_INVALID_ARG, "unknown bits in flags");
+    if (p->flags & ~(HJ_BATCH_AUTOTUNE | HJ_BATCH_REFINE | HJ_BATCH_WG1D))
+        return fail(HJ_ERR_INVALID_ARG, "unknown bits in flags");
     const bool tune = (p->flags & HJ_BATCH_AUTOTUNE) != 0;
     const bool refine = (p->flags & HJ_BATCH_REFINE) != 0;
+    const bool wg1d = (p->flags & HJ_BATCH_WG1D) != 0;
+    if (wg1d && (tune || refine))
+        return fail(HJ_ERR_UNSUPPORTED, "HJ_BATCH_WG1D does not combine with HJ_BATCH_AUTOTUNE or HJ_BATCH_REFINE");
     if (refine && dt != HJ_F64) return fail(HJ_ERR_INVALID_ARG, "refined batches take FP64 problems");
     if (refine && !(p->rel_tol > 0.0)) return fail(HJ_ERR_INVALID_ARG, "refined batches need rel_tol > 0");
     if (p->max_outer < 0) return fail(HJ_ERR_INVALID_ARG, "max_outer must be >= 0");
@@ -1312,6 +1406,7 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
     DevScratch &S = g_scr[dev];
     std::lock_guard<std::mutex> lock(S.mu);
     hipStream_t st = (hipStream_t)stream;
+    if (wg1d) return solve_batched_wg1d(probs, nprob, *p, dt, st, g_bat[dev], infos);
     hj_params P2 = p->p2, P1 = p->p1;
     if (tune && (r = tune_batch_locked(probs, nprob, dt, st, dev, S, P2, P1)) != HJ_OK) return r;
     BatchScratch &B = g_bat[dev];

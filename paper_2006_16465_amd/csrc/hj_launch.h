@@ -69,6 +69,19 @@ hipError_t launch_resid1d(int dt, const Geom1 &g, const void *f, const void *x, 
 // in ctrl from one launch to the next; every: judge every iterate (tolerance
 // mode), else only iterates 0 and maxc.
 bool solve1d_wg_supported(const Geom1 &g, int dt);
+// One problem of a one-workgroup batch (its own grid, f and x).
+struct WgProb {
+    Geom1 g;
+    const void *f;
+    void *x;
+};
+// Workgroup b solves probs[b] (device array) with state ctrls[b]; every
+// problem passes solve1d_wg_supported with tile tt; max_n, max_nt: the
+// largest n and tile count over the batch.
+hipError_t launch_solve1d_wg_batch(int dt, int tt, const WgProb *probs, int64_t nprob, int64_t max_n,
+                                   int64_t max_nt, int s, int64_t c_begin, int64_t c_end, int64_t maxc, double tol,
+                                   bool every, Ctrl *ctrls, hipStream_t st);
+hipError_t launch_ctrl_init_n(Ctrl *ctrls, int64_t n, hipStream_t st);
 hipError_t launch_solve1d_wg(int dt, const Geom1 &g, int s, const void *f, void *x, int64_t c_begin,
                              int64_t c_end, int64_t maxc, double tol, bool every, Ctrl *ctrl, hipStream_t st);
 

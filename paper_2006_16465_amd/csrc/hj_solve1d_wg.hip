@@ -17,8 +17,8 @@
 namespace hj {
 namespace {
 
-constexpr int kWgThreads = 1024;              // 16 wavefronts
-constexpr int kWgMaxTiles = kWgThreads / 64;  // one tile per wavefront
+constexpr int kWgThreads = 1024;              // launch bound; a launch has one wavefront per tile
+constexpr int kWgMaxTiles = kWgThreads / 64;  // 16
 constexpr size_t kWgMaxLds = 60 * 1024;       // f and the two iterates
 
 // v from lane CTRL selects, 0 in rows ROW_MASK leaves out.
@@ -49,31 +49,36 @@ __device__ __forceinline__ double wave_total(double v)
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
-// Cycles [c_begin, c_end) of the solve; c_end <= maxc + 1.  The pass for
-// c == maxc runs no sweep (it only evaluates the residual of iterate maxc).
-// x holds iterate c_begin on entry and, on return, the iterate the solve
-// stopped at (tolerance mode) or iterate c_end (c_end <= maxc) / maxc.
-// every: judge every iterate (tolerance mode), else only iterates 0 and maxc.
+// Cycles [c_begin, c_end) of one solve by the calling workgroup (one
+// wavefront per tile); c_end <= maxc + 1.  The pass for c == maxc runs no
+// sweep (it only evaluates the residual of iterate maxc).  x holds iterate
+// c_begin on entry and, on return, the iterate the solve stopped at
+// (tolerance mode) or iterate c_end (c_end <= maxc) / maxc.  every: judge
+// every iterate (tolerance mode), else only iterates 0 and maxc.  A solve
+// that has stopped returns at once.
 template <typename T, int TT>
-__global__ __launch_bounds__(kWgThreads) void k_solve1d_wg(Geom1 g, const T *__restrict__ f, T *__restrict__ x,
-                                                           int s, int64_t c_begin, int64_t c_end, int64_t maxc,
-                                                           double tol, int every, Ctrl *ctrl)
+__device__ __forceinline__ void solve_body(const Geom1 &g, const T *__restrict__ f, T *__restrict__ x, int s,
+                                           int64_t c_begin, int64_t c_end, int64_t maxc, double tol, int every,
+                                           Ctrl *ctrl, T *smem, double (&red)[2][kWgThreads / 64])
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[2][kWgThreads / 64];  // wavefront sums, by cycle parity
+    // Solve state, identical in every thread (read before any thread of this
+    // launch writes the block: the writes below follow at least one barrier).
+    int32_t status = ctrl->status;
+    if (every && status != ST_RUNNING) return;
+    double r0sq = ctrl->r0sq, last = ctrl->last_rsq;
+    int64_t done = ctrl->done_cycle;
+
     const int n = (int)g.n;
-    T *fl = (T *)smem;
+    const int nth = (int)blockDim.x;
+    T *fl = smem;
     T *b0 = fl + n;
     T *b1 = b0 + n;
-    for (int i = (int)threadIdx.x; i < n; i += kWgThreads) {
+    for (int i = (int)threadIdx.x; i < n; i += nth) {
         fl[i] = f[i];
         b0[i] = x[i];
     }
-    // Solve state, identical in every thread (read before any thread of this
-    // launch writes the block: the writes below follow several barriers).
-    int32_t status = ctrl->status;
-    double r0sq = ctrl->r0sq, last = ctrl->last_rsq;
-    int64_t done = ctrl->done_cycle;
+    // slots of wavefronts the workgroup does not have stay 0
+    for (int w = (int)threadIdx.x; w < 2 * kWgMaxTiles; w += nth) red[w / kWgMaxTiles][w % kWgMaxTiles] = 0.0;
     __syncthreads();
 
     int64_t c = c_begin;
@@ -91,11 +96,11 @@ __global__ __launch_bounds__(kWgThreads) void k_solve1d_wg(Geom1 g, const T *__r
         // so the next cycle's sums land in the other half while slow
         // wavefronts still read this one.
         __syncthreads();
-        double p[kWgThreads / 64];
+        double p[kWgMaxTiles];
 #pragma unroll
-        for (int w = 0; w < kWgThreads / 64; ++w) p[w] = red[odd][w];
+        for (int w = 0; w < kWgMaxTiles; ++w) p[w] = red[odd][w];
 #pragma unroll
-        for (int h = kWgThreads / 128; h >= 1; h >>= 1)
+        for (int h = kWgMaxTiles / 2; h >= 1; h >>= 1)
 #pragma unroll
             for (int w = 0; w < h; ++w) p[w] += p[w + h];
         const double tot = p[0];
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(kWgThreads) void k_solve1d_wg(Geom1 g, const T *__r
     // both buffers hold iterate maxc.
     const int64_t k = stop ? c : c_end;
     const T *res = ((k - c_begin) & 1) ? b1 : b0;
-    for (int i = (int)threadIdx.x; i < n; i += kWgThreads) x[i] = res[i];
+    for (int i = (int)threadIdx.x; i < n; i += nth) x[i] = res[i];
     if (threadIdx.x == 0) {
         ctrl->r0sq = r0sq;
         ctrl->last_rsq = last;
@@ -133,18 +138,83 @@ __global__ __launch_bounds__(kWgThreads) void k_solve1d_wg(Geom1 g, const T *__r
     }
 }
 
+// One solve; launched with 64 g.nt threads.
+template <typename T, int TT>
+__global__ __launch_bounds__(kWgThreads) void k_solve1d_wg(Geom1 g, const T *__restrict__ f, T *__restrict__ x,
+                                                           int s, int64_t c_begin, int64_t c_end, int64_t maxc,
+                                                           double tol, int every, Ctrl *ctrl)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2][kWgThreads / 64];  // wavefront sums, by cycle parity
+    solve_body<T, TT>(g, f, x, s, c_begin, c_end, maxc, tol, every, ctrl, (T *)smem, red);
+}
+
+// Workgroup b solves problem b of a batch; launched with 64 max(nt) threads.
+template <typename T, int TT>
+__global__ __launch_bounds__(kWgThreads) void k_solve1d_wg_batch(const WgProb *__restrict__ probs, int s,
+                                                                 int64_t c_begin, int64_t c_end, int64_t maxc,
+                                                                 double tol, int every, Ctrl *ctrls)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2][kWgThreads / 64];
+    const WgProb q = probs[blockIdx.x];
+    solve_body<T, TT>(q.g, (const T *)q.f, (T *)q.x, s, c_begin, c_end, maxc, tol, every, ctrls + blockIdx.x,
+                      (T *)smem, red);
+}
+
+__global__ void k_ctrl_init_n(Ctrl *ctrls, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Ctrl c;
+    c.r0sq = 0.0;
+    c.last_rsq = 0.0;
+    c.iter = 0;
+    c.done_cycle = -1;
+    c.stop_at = INT64_MAX;
+    c.status = ST_RUNNING;
+    c.pad = 0;
+    ctrls[i] = c;
+}
+
 template <typename T>
 hipError_t launch_t(const Geom1 &g, int s, const void *f, void *x, int64_t c_begin, int64_t c_end, int64_t maxc,
                     double tol, bool every, Ctrl *ctrl, hipStream_t st)
 {
     const size_t lds = 3 * (size_t)g.n * sizeof(T);
     const int ev = every ? 1 : 0;
+    const unsigned nth = 64u * (unsigned)g.nt;  // one wavefront per tile
 #define HJ_WG(TT)                                                                                            \
     case TT:                                                                                                 \
-        k_solve1d_wg<T, TT><<<1, kWgThreads, lds, st>>>(g, (const T *)f, (T *)x, s, c_begin, c_end, maxc, tol, \
-                                                        ev, ctrl);                                           \
+        k_solve1d_wg<T, TT><<<1, nth, lds, st>>>(g, (const T *)f, (T *)x, s, c_begin, c_end, maxc, tol, ev, \
+                                                 ctrl);                                                      \
         break;
     switch (g.t) {
+        HJ_WG(64)
+        HJ_WG(128)
+        HJ_WG(256)
+        HJ_WG(512)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef HJ_WG
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch_t(int tt, const WgProb *probs, int64_t nprob, int64_t max_n, int64_t max_nt, int s,
+                          int64_t c_begin, int64_t c_end, int64_t maxc, double tol, bool every, Ctrl *ctrls,
+                          hipStream_t st)
+{
+    const size_t lds = 3 * (size_t)max_n * sizeof(T);
+    const int ev = every ? 1 : 0;
+    const unsigned nth = 64u * (unsigned)max_nt;
+    const unsigned nb = (unsigned)nprob;
+#define HJ_WG(TT)                                                                                               \
+    case TT:                                                                                                    \
+        k_solve1d_wg_batch<T, TT><<<nb, nth, lds, st>>>(probs, s, c_begin, c_end, maxc, tol, ev, ctrls);       \
+        break;
+    switch (tt) {
         HJ_WG(64)
         HJ_WG(128)
         HJ_WG(256)
@@ -168,10 +238,29 @@ bool solve1d_wg_supported(const Geom1 &g, int dt)
 hipError_t launch_solve1d_wg(int dt, const Geom1 &g, int s, const void *f, void *x, int64_t c_begin,
                              int64_t c_end, int64_t maxc, double tol, bool every, Ctrl *ctrl, hipStream_t st)
 {
-    if (!solve1d_wg_supported(g, dt) || c_begin < 0 || c_end <= c_begin || c_end > maxc + 1 || s < 1)
+    if (!solve1d_wg_supported(g, dt) || c_begin < 0 || c_end <= c_begin || c_end - 1 > maxc || s < 1)
         return hipErrorInvalidValue;
     if (dt == F64) return launch_t<double>(g, s, f, x, c_begin, c_end, maxc, tol, every, ctrl, st);
     return launch_t<float>(g, s, f, x, c_begin, c_end, maxc, tol, every, ctrl, st);
+}
+
+hipError_t launch_solve1d_wg_batch(int dt, int tt, const WgProb *probs, int64_t nprob, int64_t max_n,
+                                   int64_t max_nt, int s, int64_t c_begin, int64_t c_end, int64_t maxc, double tol,
+                                   bool every, Ctrl *ctrls, hipStream_t st)
+{
+    const size_t es = dt == F64 ? sizeof(double) : sizeof(float);
+    if (nprob < 1 || nprob > INT32_MAX || max_nt < 1 || max_nt > kWgMaxTiles || max_n < 1 ||
+        3 * (size_t)max_n * es > kWgMaxLds || c_begin < 0 || c_end <= c_begin || c_end - 1 > maxc || s < 1)
+        return hipErrorInvalidValue;
+    if (dt == F64) return launch_batch_t<double>(tt, probs, nprob, max_n, max_nt, s, c_begin, c_end, maxc, tol, every, ctrls, st);
+    return launch_batch_t<float>(tt, probs, nprob, max_n, max_nt, s, c_begin, c_end, maxc, tol, every, ctrls, st);
+}
+
+hipError_t launch_ctrl_init_n(Ctrl *ctrls, int64_t n, hipStream_t st)
+{
+    if (n < 1) return hipSuccess;
+    k_ctrl_init_n<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(ctrls, n);
+    return hipGetLastError();
 }
 
 }  // namespace hj

@@ -86,6 +86,7 @@ class BatchParams(ctypes.Structure):
 
 HJ_BATCH_AUTOTUNE = 0x1
 HJ_BATCH_REFINE = 0x2
+HJ_BATCH_WG1D = 0x4
 
 
 class _Info(ctypes.Structure):
@@ -349,7 +350,7 @@ def autotune_batch(problems):
 
 def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 18), tile_1d=256,
                   s_1d=16, overlap_1d=30, max_cycles=1_000_000, graph_cycles=8, autotune=False,
-                  refine=False, max_outer=0, allow_not_converged=False) -> list:
+                  refine=False, max_outer=0, allow_not_converged=False, one_workgroup_1d=False) -> list:
     """Solve many independent problems together (hj_solve_batched).
 
     problems: sequence of (f, x, h) or (f, x, hx, hy); f, x GPU tensors of one
@@ -362,7 +363,10 @@ def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 1
     refinement (at most max_outer correction solves, 0 = 8; a problem whose
     FP32 solve stops converging, or whose F is too large, continues in FP64).
     max_cycles bounds every problem's cycles over all phases.  Info.cycles
-    counts the cycles inside each result.  Returns one Info per problem."""
+    counts the cycles inside each result.  one_workgroup_1d=True (1D problems
+    only, tile_1d of 64-512, at most 16 tiles and 60 KiB of f and iterates per
+    problem): each problem runs its whole solve inside one workgroup, one
+    launch for the batch.  Returns one Info per problem."""
     import torch
     if not problems:
         return []
@@ -374,7 +378,8 @@ def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 1
     bp.max_cycles = max_cycles
     bp.dtype = dt
     bp.graph_cycles = graph_cycles
-    bp.flags = (HJ_BATCH_AUTOTUNE if autotune else 0) | (HJ_BATCH_REFINE if refine else 0)
+    bp.flags = ((HJ_BATCH_AUTOTUNE if autotune else 0) | (HJ_BATCH_REFINE if refine else 0) |
+                (HJ_BATCH_WG1D if one_workgroup_1d else 0))
     bp.max_outer = max_outer
     infos = (_Info * len(problems))()
     f0 = problems[0][0]

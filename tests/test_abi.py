@@ -158,7 +158,8 @@ def _batch(n2=1, n1=1, **kw):
     ({"dtype": 7}, hj.HJ_ERR_INVALID_ARG),
     ({"max_cycles": 0}, hj.HJ_ERR_INVALID_ARG),
     ({"graph_cycles": 2000}, hj.HJ_ERR_INVALID_ARG),
-    ({"flags": 4}, hj.HJ_ERR_INVALID_ARG),
+    ({"flags": 8}, hj.HJ_ERR_INVALID_ARG),
+    ({"flags": 6}, hj.HJ_ERR_UNSUPPORTED),              # HJ_BATCH_WG1D with HJ_BATCH_REFINE
     ({"rel_tol": float("nan")}, hj.HJ_ERR_INVALID_ARG),
     ({"q_nx": 40, "q_ld": 40}, hj.HJ_ERR_UNSUPPORTED),   # 2D problem smaller than the tile
 ])

@@ -122,3 +122,65 @@ def test_wg_nonfinite_input_stops_like_per_cycle_launches():
             hj.solve_1d(dev(f), dev(np.zeros(n)), h, tile=64, s=8, overlap=14, rel_tol=1e-6,
                         launch_per_cycle=per_cycle)
         assert e.value.status == hj.HJ_ERR_NONFINITE
+
+
+def _batch_specs(count, seed):
+    rng = np.random.default_rng(seed)
+    return [(int(n), W.rhs_1d_modes(int(n), 8, 100 + i)) for i, n in enumerate(rng.integers(37, 2501, count))]
+
+
+@pytest.mark.parametrize("mode", ["to_tol", "fixed", "capped"])
+def test_wg_batch_matches_single_solves_and_oracle(orc, mode):
+    """HJ_BATCH_WG1D: ragged 1D sizes (37..2500 points, 1 to 11 tiles of 256,
+    s = 16, overlap 30), one workgroup per problem; every problem's iterate
+    and info equal its own hj_solve_1d call, and the oracle's."""
+    specs = _batch_specs(24, 4)
+    kw = {"to_tol": dict(rel_tol=1e-6, max_cycles=100_000),
+          "fixed": dict(rel_tol=0.0, max_cycles=7),
+          "capped": dict(rel_tol=1e-9, max_cycles=5)}[mode]
+    shape = dict(tile_1d=256, s_1d=16, overlap_1d=30)
+    say(f"wg batch {mode}: {len(specs)} problems")
+    Fs = [dev(f) for _, f in specs]
+    Xs = [dev(np.zeros(n)) for n, _ in specs]
+    infos = hj.solve_batched([(F, X, 1.0 / (n + 1)) for F, X, (n, _) in zip(Fs, Xs, specs)],
+                             one_workgroup_1d=True, allow_not_converged=True, **shape, **kw)
+    for i, ((n, f), F, X, ib) in enumerate(zip(specs, Fs, Xs, infos)):
+        X1 = dev(np.zeros(n))
+        i1 = hj.solve_1d(F, X1, 1.0 / (n + 1), tile=256, s=16, overlap=30, allow_not_converged=True, **kw)
+        assert ib.cycles == i1.cycles and ib.sweeps == i1.sweeps, i
+        assert ib.status == i1.status, i
+        assert np.array_equal(host(X), host(X1)), i
+        assert abs(ib.rel_residual - i1.rel_residual) <= 1e-13 * i1.rel_residual, i
+        if mode == "capped":
+            assert ib.cycles == 5 and ib.status == hj.HJ_ERR_NOT_CONVERGED
+        if i < 4:
+            h = 1.0 / (n + 1)
+            if mode == "fixed":
+                want = orc.hier_1d(f, np.zeros(n), h, 256, 16, 7, 30)
+            else:
+                want, co, _, _ = orc.solve_1d(f, np.zeros(n), h, tile=256, s=16, tol=kw["rel_tol"],
+                                              overlap=30, max_cycles=kw["max_cycles"])
+                assert ib.cycles == (co if co >= 0 else kw["max_cycles"]), i
+            assert np.array_equal(host(X), want), i
+
+
+def test_wg_batch_rejects_what_one_workgroup_cannot_hold():
+    n = 256
+    f = dev(W.rhs_1d_modes(n, 8, 0))
+    prob = [(f, dev(np.zeros(n)), 1.0 / (n + 1))]
+    for kw in (dict(tile_1d=32, s_1d=8, overlap_1d=0),         # LDS tile body
+               dict(tile_1d=64, s_1d=8, overlap_1d=0, autotune=True)):
+        with pytest.raises(hj.HJError) as e:
+            hj.solve_batched(prob, one_workgroup_1d=True, **kw)
+        assert e.value.status == hj.HJ_ERR_UNSUPPORTED
+    big = 5000  # 3 n 8 B > 60 KiB
+    fb = dev(W.rhs_1d_modes(big, 8, 0))
+    with pytest.raises(hj.HJError) as e:
+        hj.solve_batched([(fb, dev(np.zeros(big)), 1.0 / (big + 1))], one_workgroup_1d=True,
+                         tile_1d=512, s_1d=8, overlap_1d=14)
+    assert e.value.status == hj.HJ_ERR_UNSUPPORTED
+    f2 = dev(W.rhs_2d_modes(64, 64, 4, 0.0, 0))
+    with pytest.raises(hj.HJError) as e:
+        hj.solve_batched([(f2, dev(np.zeros((64, 64))), 1.0 / 65)], one_workgroup_1d=True, tile=(32, 32), s=4,
+                         overlap=(0, 0))
+    assert e.value.status == hj.HJ_ERR_UNSUPPORTED
