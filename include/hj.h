@@ -218,7 +218,9 @@ typedef struct hj_problem {
  * tile_x in {64, 128, 256, 512} and every problem at most 16 tiles with 3 n
  * element sizes of at most 60 KiB; not with HJ_BATCH_AUTOTUNE or
  * HJ_BATCH_REFINE (HJ_ERR_UNSUPPORTED otherwise).  Iterates, cycle counts
- * and infos are those of each problem's own hj_solve_1d call. */
+ * and infos are those of each problem's own hj_solve_1d call.  graph_cycles
+ * is ignored; the scratch is a device copy of the problem table and one
+ * solve state per problem (no iterate arrays). */
 #define HJ_BATCH_WG1D 0x4
 
 typedef struct hj_batch_params {
