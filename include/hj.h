@@ -93,8 +93,10 @@ typedef enum hj_method { HJ_HIERARCHICAL = 0, HJ_GLOBAL = 1 } hj_method;
 /* hj_params.flags, 1D hierarchical solves: one kernel launch per cycle even
  * where one workgroup can run the whole solve (same iterates; for comparison
  * and testing).  Without it, a 1D hierarchical solve with tiles of 64, 128,
- * 256 or 512 points, at most 16 tiles and 3 n element sizes of at most
- * 60 KiB runs all its cycles inside one workgroup (Sec. 3.3 cycle, global
+ * 256 or 512 points, at most 16 tiles and 3 n element sizes within the
+ * workgroup's LDS (150 KiB on gfx950: the device's opt-in limit per
+ * workgroup less 1 KiB, at most 150 KiB; 60 KiB where the device reports no
+ * opt-in limit) runs all its cycles inside one workgroup (Sec. 3.3 cycle, global
  * iterates in LDS, the residual judged on the device every cycle). */
 #define HJ_FLAG_LAUNCH_PER_CYCLE 0x2
 
@@ -216,7 +218,8 @@ typedef struct hj_problem {
  * every problem's cycles (in launches of up to 4096 cycles), the iterates and
  * f in LDS, as hj_solve_1d runs a small grid.  Needs p1 hierarchical with
  * tile_x in {64, 128, 256, 512} and every problem at most 16 tiles with 3 n
- * element sizes of at most 60 KiB; not with HJ_BATCH_AUTOTUNE or
+ * element sizes within the workgroup's LDS (as for HJ_FLAG_LAUNCH_PER_CYCLE
+ * above); not with HJ_BATCH_AUTOTUNE or
  * HJ_BATCH_REFINE (HJ_ERR_UNSUPPORTED otherwise).  Iterates, cycle counts
  * and infos are those of each problem's own hj_solve_1d call.  graph_cycles
  * is ignored; the scratch is a device copy of the problem table and one

@@ -1274,7 +1274,7 @@ hj_status solve_batched_wg1d(const hj_problem *probs, int64_t nprob, const hj_ba
         if (!hj::solve1d_wg_supported(g, dt))
             return fail(HJ_ERR_UNSUPPORTED, "problem " + std::to_string(i) +
                                                 ": HJ_BATCH_WG1D needs tiles of 64..512 points, at most 16 tiles "
-                                                "and 3 n element sizes of at most 60 KiB");
+                                                "and 3 n element sizes within the workgroup's LDS (150 KiB on gfx950)");
         table[(size_t)i] = hj::WgProb{g, q.f, q.x};
         max_n = std::max(max_n, g.n);
         max_nt = std::max(max_nt, g.nt);

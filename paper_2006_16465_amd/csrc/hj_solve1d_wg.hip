@@ -11,6 +11,8 @@
 // so the solve stops at the same iterate as the per-cycle path, and the
 // iterates agree with it bit for bit.  At the paper's 1D size (256 points) a
 // cycle then costs about a microsecond instead of a launch.
+#include <algorithm>
+
 #include "hj_launch.h"
 #include "hj_tiles.h"
 
@@ -19,7 +21,35 @@ namespace {
 
 constexpr int kWgThreads = 1024;              // launch bound; a launch has one wavefront per tile
 constexpr int kWgMaxTiles = kWgThreads / 64;  // 16
-constexpr size_t kWgMaxLds = 60 * 1024;       // f and the two iterates
+constexpr size_t kWgLdsCap = 150 * 1024;      // f and the two iterates, at most
+constexpr size_t kWgLdsDefault = 60 * 1024;   // without the device's opt-in limit
+
+// LDS a workgroup may take for f and the iterates on the current device: the
+// opt-in limit per workgroup (160 KiB on gfx950) less the static arrays,
+// capped at kWgLdsCap; 60 KiB if the device does not report it.
+size_t wg_max_lds()
+{
+    static size_t cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return kWgLdsDefault;
+    if (!cache[dev]) {
+        int v = 0;
+        size_t lim = kWgLdsDefault;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) == hipSuccess &&
+            v > 2048)
+            lim = std::min(kWgLdsCap, std::max(kWgLdsDefault, (size_t)v - 1024));
+        cache[dev] = lim;
+    }
+    return cache[dev];
+}
+
+// Dynamic LDS above the default 64 KiB needs the kernel's opt-in.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds)
+{
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
 
 // v from lane CTRL selects, 0 in rows ROW_MASK leaves out.
 template <int CTRL, int ROW_MASK>
@@ -186,6 +216,7 @@ hipError_t launch_t(const Geom1 &g, int s, const void *f, void *x, int64_t c_beg
     const unsigned nth = 64u * (unsigned)g.nt;  // one wavefront per tile
 #define HJ_WG(TT)                                                                                            \
     case TT:                                                                                                 \
+        if (hipError_t e = allow_lds(k_solve1d_wg<T, TT>, lds); e != hipSuccess) return e;                   \
         k_solve1d_wg<T, TT><<<1, nth, lds, st>>>(g, (const T *)f, (T *)x, s, c_begin, c_end, maxc, tol, ev, \
                                                  ctrl);                                                      \
         break;
@@ -212,6 +243,7 @@ hipError_t launch_batch_t(int tt, const WgProb *probs, int64_t nprob, int64_t ma
     const unsigned nb = (unsigned)nprob;
 #define HJ_WG(TT)                                                                                               \
     case TT:                                                                                                    \
+        if (hipError_t e = allow_lds(k_solve1d_wg_batch<T, TT>, lds); e != hipSuccess) return e;               \
         k_solve1d_wg_batch<T, TT><<<nb, nth, lds, st>>>(probs, s, c_begin, c_end, maxc, tol, ev, ctrls);       \
         break;
     switch (tt) {
@@ -232,7 +264,7 @@ bool solve1d_wg_supported(const Geom1 &g, int dt)
 {
     const size_t es = dt == F64 ? sizeof(double) : sizeof(float);
     const bool tile = g.t == 64 || g.t == 128 || g.t == 256 || g.t == 512;
-    return tile && g.nt >= 1 && g.nt <= kWgMaxTiles && 3 * (size_t)g.n * es <= kWgMaxLds;
+    return tile && g.nt >= 1 && g.nt <= kWgMaxTiles && 3 * (size_t)g.n * es <= wg_max_lds();
 }
 
 hipError_t launch_solve1d_wg(int dt, const Geom1 &g, int s, const void *f, void *x, int64_t c_begin,
@@ -250,7 +282,7 @@ hipError_t launch_solve1d_wg_batch(int dt, int tt, const WgProb *probs, int64_t 
 {
     const size_t es = dt == F64 ? sizeof(double) : sizeof(float);
     if (nprob < 1 || nprob > INT32_MAX || max_nt < 1 || max_nt > kWgMaxTiles || max_n < 1 ||
-        3 * (size_t)max_n * es > kWgMaxLds || c_begin < 0 || c_end <= c_begin || c_end - 1 > maxc || s < 1)
+        3 * (size_t)max_n * es > wg_max_lds() || c_begin < 0 || c_end <= c_begin || c_end - 1 > maxc || s < 1)
         return hipErrorInvalidValue;
     if (dt == F64) return launch_batch_t<double>(tt, probs, nprob, max_n, max_nt, s, c_begin, c_end, maxc, tol, every, ctrls, st);
     return launch_batch_t<float>(tt, probs, nprob, max_n, max_nt, s, c_begin, c_end, maxc, tol, every, ctrls, st);

@@ -234,7 +234,7 @@ def solve_1d(f, x, h, *, tile=32, s=16, method="hierarchical", rel_tol=1e-6, max
              check_every=0, overlap=0, allow_not_converged=False, launch_per_cycle=False) -> Info:
     """Solve -u'' = f (n interior points, spacing h) in place in x (hj_solve_1d).
     Small hierarchical solves (tiles of 64-512 points, at most 16 tiles, f and
-    two iterates within 60 KiB) run all their cycles in one workgroup;
+    two iterates within 150 KiB of LDS) run all their cycles in one workgroup;
     launch_per_cycle=True forces one kernel launch per cycle (same iterates)."""
     _check_pair(f, x)
     if f.dim() != 1 or not f.is_contiguous() or not x.is_contiguous():
@@ -364,7 +364,7 @@ def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 1
     FP32 solve stops converging, or whose F is too large, continues in FP64).
     max_cycles bounds every problem's cycles over all phases.  Info.cycles
     counts the cycles inside each result.  one_workgroup_1d=True (1D problems
-    only, tile_1d of 64-512, at most 16 tiles and 60 KiB of f and iterates per
+    only, tile_1d of 64-512, at most 16 tiles and 150 KiB of f and iterates per
     problem): each problem runs its whole solve inside one workgroup, one
     launch for the batch.  Returns one Info per problem."""
     import torch

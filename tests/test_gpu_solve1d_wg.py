@@ -17,10 +17,11 @@ torch = pytest.importorskip("torch")
 
 # (n, tile, s, overlap): 5 tiles (the paper's 1D size with exact-regime
 # overlap), 16 tiles (the most one workgroup holds, ragged last tile), a grid
-# shorter than the tile, 2 and 6 tiles, f and both iterates filling the 60 KiB
-# of LDS at FP64 (n = 2560).
+# shorter than the tile, 2, 6 and 11 tiles; f and both iterates take 60 KiB
+# of LDS at n = 2560 and 117 KiB at n = 5000 (above the 64 KiB a workgroup
+# gets without opting in).
 SHAPES = [(256, 64, 8, 14), (1000, 64, 8, 0), (37, 64, 5, 0), (700, 128, 6, 10), (300, 256, 3, 0),
-          (2560, 512, 24, 46)]
+          (2560, 512, 24, 46), (5000, 512, 24, 46)]
 
 
 def say(*a):
@@ -84,8 +85,8 @@ def test_wg_to_tolerance_matches_oracle(orc, n, tile, s, ov):
 
 
 def test_wg_fp32_matches_per_cycle_launches():
-    """FP32 at the largest FP32 grid the workgroup holds (3 n 4 B <= 60 KiB)."""
-    n, tile, s, ov = 5000, 512, 8, 14
+    """FP32 near the largest grid one workgroup holds (15 tiles of 512)."""
+    n, tile, s, ov = 7000, 512, 8, 14
     f = W.rhs_1d_modes(n, 8, 2)
     h = 1.0 / (n + 1)
     say(f"wg fp32 n={n}")
@@ -173,7 +174,7 @@ def test_wg_batch_rejects_what_one_workgroup_cannot_hold():
         with pytest.raises(hj.HJError) as e:
             hj.solve_batched(prob, one_workgroup_1d=True, **kw)
         assert e.value.status == hj.HJ_ERR_UNSUPPORTED
-    big = 5000  # 3 n 8 B > 60 KiB
+    big = 7000  # 3 n 8 B > 150 KiB
     fb = dev(W.rhs_1d_modes(big, 8, 0))
     with pytest.raises(hj.HJError) as e:
         hj.solve_batched([(fb, dev(np.zeros(big)), 1.0 / (big + 1))], one_workgroup_1d=True,
