@@ -185,3 +185,22 @@ def test_wg_batch_rejects_what_one_workgroup_cannot_hold():
         hj.solve_batched([(f2, dev(np.zeros((64, 64))), 1.0 / 65)], one_workgroup_1d=True, tile=(32, 32), s=4,
                          overlap=(0, 0))
     assert e.value.status == hj.HJ_ERR_UNSUPPORTED
+
+
+def test_wg_batch_fp32_matches_single_solves():
+    """FP32 batch (37..2500 points, at most 10 tiles of 256): each problem
+    equals its own FP32 hj_solve_1d call bit for bit."""
+    specs = _batch_specs(8, 7)
+    say(f"wg batch fp32: {len(specs)} problems")
+    Fs = [dev(f, torch.float32) for _, f in specs]
+    Xs = [dev(np.zeros(n), torch.float32) for n, _ in specs]
+    infos = hj.solve_batched([(F, X, 1.0 / (n + 1)) for F, X, (n, _) in zip(Fs, Xs, specs)], rel_tol=1e-4,
+                             max_cycles=100_000, tile_1d=256, s_1d=8, overlap_1d=14, one_workgroup_1d=True,
+                             allow_not_converged=True)
+    for i, ((n, _), F, X, ib) in enumerate(zip(specs, Fs, Xs, infos)):
+        assert hj.axis_tiles(n, 256, 14) <= 16
+        X1 = dev(np.zeros(n), torch.float32)
+        i1 = hj.solve_1d(F, X1, 1.0 / (n + 1), tile=256, s=8, overlap=14, rel_tol=1e-4, max_cycles=100_000,
+                         allow_not_converged=True)
+        assert ib.cycles == i1.cycles and ib.status == i1.status, i
+        assert np.array_equal(host(X), host(X1)), i
