@@ -90,14 +90,18 @@ typedef enum hj_method { HJ_HIERARCHICAL = 0, HJ_GLOBAL = 1 } hj_method;
 /* hj_params.flags: run every 2D cycle on the LDS ping-pong kernel instead of
  * the register-resident one (same iterates; for comparison and testing). */
 #define HJ_FLAG_LDS_KERNEL 0x1
-/* hj_params.flags, 1D hierarchical solves: one kernel launch per cycle even
- * where one workgroup can run the whole solve (same iterates; for comparison
- * and testing).  Without it, a 1D hierarchical solve with tiles of 64, 128,
- * 256 or 512 points, at most 16 tiles and 3 n element sizes within the
- * workgroup's LDS (150 KiB on gfx950: the device's opt-in limit per
+/* hj_params.flags, 1D solves: one kernel launch per cycle (HJ_GLOBAL: per
+ * sweep) even where one workgroup can run the whole solve (same iterates; for
+ * comparison and testing).  Without it, a 1D hierarchical solve with tiles of
+ * 64, 128, 256 or 512 points, at most 16 tiles and 3 n element sizes within
+ * the workgroup's LDS (150 KiB on gfx950: the device's opt-in limit per
  * workgroup less 1 KiB, at most 150 KiB; 60 KiB where the device reports no
- * opt-in limit) runs all its cycles inside one workgroup (Sec. 3.3 cycle, global
- * iterates in LDS, the residual judged on the device every cycle). */
+ * opt-in limit) runs all its cycles inside one workgroup (Sec. 3.3 cycle,
+ * global iterates in LDS, the residual judged on the device every cycle).
+ * HJ_GLOBAL solves of such grids run the same way as cycles of one
+ * sub-iteration without overlap on the smallest tile of 64..512 points that
+ * covers the grid in at most 16 tiles: these are classical sweeps exactly
+ * (Sec. 3.3, k = 1), so both methods pay the same (no) launch cost. */
 #define HJ_FLAG_LAUNCH_PER_CYCLE 0x2
 
 typedef struct hj_params {

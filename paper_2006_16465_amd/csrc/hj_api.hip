@@ -1132,6 +1132,23 @@ hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *
         if ((r = scratch_ensure(S, 0, 0)) != HJ_OK) return r;
         return drive_1d_wg(g, dt, P, f, x, st, S, info);
     }
+    if (!hier && !(P.flags & HJ_FLAG_LAUNCH_PER_CYCLE)) {
+        // Classical Jacobi is the cycle with one sub-iteration and no overlap
+        // (Sec. 3.3: k = 1 is exactly Jacobi), so a grid that fits one
+        // workgroup runs its sweeps there too, launch-free like the
+        // hierarchical solve: the smallest tile that covers the grid in at
+        // most 16 tiles.
+        for (const int t : {64, 128, 256, 512}) {
+            hj_params Q = P;
+            Q.tile_x = t;
+            Q.overlap_x = 0;
+            Q.s = 1;
+            const hj::Geom1 gq = make_geom1(n, h, &Q);
+            if (!hj::solve1d_wg_supported(gq, dt)) continue;
+            if ((r = scratch_ensure(S, 0, 0)) != HJ_OK) return r;
+            return drive_1d_wg(gq, dt, Q, f, x, st, S, info);
+        }
+    }
     const int64_t nbc = hier ? hj::cycle1d_blocks(g) : hj::sweep1d_blocks(g);
     const int64_t nbr = hj::resid1d_blocks(g);
     if (nbc > INT32_MAX || nbr > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "grid too large");
@@ -1503,12 +1520,24 @@ hj_status hj_solve_adjoint(const hj_adjoint_desc *d, void *stream, hj_info *info
 {
     g_err.clear();
     if (!d) return fail(HJ_ERR_INVALID_ARG, "descriptor is NULL");
-    hj_status r = hj_solve_vc_2d(&d->prob, d->dl_du, d->lam, &d->params, stream, infos);
-    if (r != HJ_OK) return r;
+    // everything the gradient step needs is checked before the solve runs
+    hj_status r;
+    if ((r = check_vc_problem(&d->prob)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(d->dl_du, HJ_F64, "dl_du", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(d->lam, HJ_F64, "lam", false)) != HJ_OK) return r;
     if (d->dl_da) {
-        if (!d->u) return fail(HJ_ERR_INVALID_ARG, "u is NULL");
-        return hj_vc_grad_a(&d->prob, d->u, d->lam, d->dl_da, d->ld_grad, stream);
+        if (!d->u) return fail(HJ_ERR_INVALID_ARG, "u is NULL while dl_da is requested");
+        if ((r = check_ptr_dtype(d->u, HJ_F64, "u", false)) != HJ_OK) return r;
+        if ((r = check_ptr_dtype(d->dl_da, HJ_F64, "dl_da", false)) != HJ_OK) return r;
+        if (d->ld_grad < d->prob.nx + 2) return fail(HJ_ERR_INVALID_ARG, "ld_grad must be >= nx + 2");
+        int dev = 0;
+        HJ_HIP(hipGetDevice(&dev));
+        if ((r = check_device_ptr(d->u, dev, "u")) != HJ_OK) return r;
+        if ((r = check_device_ptr(d->dl_da, dev, "dl_da")) != HJ_OK) return r;
     }
+    r = hj_solve_vc_2d(&d->prob, d->dl_du, d->lam, &d->params, stream, infos);
+    if (r != HJ_OK) return r;
+    if (d->dl_da) return hj_vc_grad_a(&d->prob, d->u, d->lam, d->dl_da, d->ld_grad, stream);
     return HJ_OK;
 }
 

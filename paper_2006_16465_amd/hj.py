@@ -477,13 +477,50 @@ def vc_grad_a(a, u, lam, h=None, *, hx=None, hy=None):
     return grad
 
 
+def solve_adjoint(a, u, dl_du, lam, h=None, *, hx=None, hy=None, tile=(32, 32), s=8, overlap=(0, 0),
+                  method="hierarchical", rel_tol=1e-10, max_cycles=1_000_000, check_every=0, grad_a=True,
+                  allow_not_converged=False):
+    """Backward pass of the variable-coefficient solve (hj_solve_adjoint): solves
+    A(a) lam_b = dL/du_b in place in lam (lam holds the initial guess on entry;
+    A is symmetric, so this is the forward solve on dL/du), which is dL/df, and,
+    with grad_a, dL/da from the forward states u and lam summed over the batch.
+    u, dl_du, lam: (ny, nx) or (batch, ny, nx) contiguous FP64; a: (ny+2, nx+2).
+    Returns (infos, dl_da or None)."""
+    import torch
+    hx = hx if hx is not None else h
+    hy = hy if hy is not None else hx
+    _check_pair(dl_du, lam)
+    pr = _vc_problem(a, dl_du, hx, hy)
+    if not lam.is_contiguous():
+        raise ValueError("lam must be contiguous")
+    if grad_a and (u.shape != dl_du.shape or u.dtype != dl_du.dtype or not u.is_cuda or not u.is_contiguous()):
+        raise ValueError("u must match dl_du")
+    d = AdjointDesc()
+    d.prob = pr
+    d.u = u.data_ptr() if grad_a else None
+    d.dl_du = dl_du.data_ptr()
+    d.lam = lam.data_ptr()
+    grad = torch.empty_like(a) if grad_a else None
+    d.dl_da = grad.data_ptr() if grad_a else None
+    d.ld_grad = a.shape[1]
+    d.params = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap)
+    infos = (_Info * pr.batch)()
+    with _device(dl_du):
+        st = load().hj_solve_adjoint(ctypes.byref(d), _stream(dl_du), infos)
+    out = [Info(st, i.cycles, i.sweeps, i.rel_residual, i.r0_norm) for i in infos]
+    if st == HJ_OK or (st == HJ_ERR_NOT_CONVERGED and allow_not_converged):
+        return out, grad
+    raise HJError(st, last_error())
+
+
 def _diffusion_fn():
     import torch
 
     class DiffusionSolve(torch.autograd.Function):
-        """u = A(a)^-1 f for -div(a grad u) = f.  Backward: one adjoint solve
-        A lam = dL/du (A is symmetric), dL/df = lam, dL/da from the face
-        products of u and lam.  Only the converged u (and a) are stored."""
+        """u = A(a)^-1 f for -div(a grad u) = f.  Backward: one call of
+        hj_solve_adjoint -- the adjoint solve A lam = dL/du (A is symmetric),
+        dL/df = lam, and dL/da from the face products of u and lam.  Only the
+        converged u (and a) are stored."""
 
         @staticmethod
         def forward(ctx, f, a, opts):
@@ -500,8 +537,7 @@ def _diffusion_fn():
             u, a = ctx.saved_tensors
             g = grad_u.contiguous()
             lam = torch.zeros_like(g)
-            solve_vc_2d(a, g, lam, **ctx.opts)
-            grad_a = vc_grad_a(a, u, lam, hx=ctx.opts["hx"], hy=ctx.opts["hy"])
+            _, grad_a = solve_adjoint(a, u, g, lam, grad_a=ctx.needs_input_grad[1], **ctx.opts)
             return lam, grad_a, None
 
     return DiffusionSolve

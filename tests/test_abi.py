@@ -218,6 +218,22 @@ def test_variable_coefficient_entry_points_validate():
     pr = prob()
     assert lib.hj_vc_grad_a(ctypes.byref(pr), FAKE, FAKE, FAKE, 9, None) == hj.HJ_ERR_INVALID_ARG
     assert lib.hj_solve_adjoint(None, None, None) == hj.HJ_ERR_INVALID_ARG
+    # the adjoint descriptor is checked whole before its solve runs: a
+    # requested gradient without forward states, a short gradient pitch, a
+    # misaligned or missing pointer, or a bad problem all fail up front
+    def desc(**kw):
+        d = hj.AdjointDesc()
+        d.prob = prob()
+        d.u, d.dl_du, d.lam, d.dl_da, d.ld_grad = FAKE, FAKE, FAKE, FAKE, 10
+        d.params = _params()
+        for k, v in kw.items():
+            setattr(d, k, v)
+        return d
+    for kw in ({"u": None}, {"ld_grad": 9}, {"dl_du": None}, {"lam": None}, {"lam": FAKE + 4},
+               {"dl_da": FAKE + 2}, {"prob": prob(nx=0)}):
+        d = desc(**kw)
+        assert lib.hj_solve_adjoint(ctypes.byref(d), None, info) == hj.HJ_ERR_INVALID_ARG, kw
+        assert hj.last_error(), kw
 
 
 def test_status_strings_and_defaults():

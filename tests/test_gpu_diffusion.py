@@ -3,6 +3,7 @@ adjoint: forward iterates and cycles-to-tolerance against the CPU oracle, the
 gradient with respect to a against the oracle's face-product formula (itself
 pinned by finite differences of direct solves), and torch autograd through the
 adjoint solve against central finite differences."""
+import ctypes
 import sys
 
 import numpy as np
@@ -145,3 +146,85 @@ def test_adjoint_solve_and_autograd_against_finite_differences(orc):
             Fm[b, r, q] -= eps
             fd = (loss_of(dev(a0), Fp) - loss_of(dev(a0), Fm)).item() / (2 * eps)
             assert abs(fd - gf[b, r, q]) <= 1e-4 * np.max(np.abs(gf))
+
+
+@pytest.mark.parametrize("mode", ["fixed", "tol"])
+def test_solve_adjoint_c_abi_pitched_batch(orc, mode):
+    """hj_solve_adjoint called through the C ABI on a batch of 3 right-hand
+    sides in pitched storage: f/u/lam rows of ld > nx, a batch stride beyond
+    ny * ld, coefficient rows of lda > nx + 2 and gradient rows of
+    ld_grad > nx + 2, starting from a nonzero guess.  lam equals the oracle's
+    solve of dL/du bit for bit (fixed cycles; to tolerance also the cycle
+    counts), dL/da equals the oracle's face-product gradient summed over the
+    batch within 1e-12, and no padding element is written (NaN padding in the
+    inputs would also show any read of it in the results)."""
+    ny, nx, B = 40, 56, 3
+    ld, lda, ldg = nx + 5, nx + 2 + 3, nx + 2 + 6
+    bstride = ny * ld + 37
+    hx, hy = 1.0 / (nx + 1), 1.0 / (ny + 1)
+    a = np.exp(W.grf_2d(ny + 2, nx + 2, 0.15, 1.0, hx, seed=5))
+    u = [W.rhs_random((ny, nx), 40 + b) for b in range(B)]
+    dl = [W.rhs_2d_modes(nx, ny, 6, 0.1, 50 + b) for b in range(B)]
+    lam0 = [W.rhs_random((ny, nx), 60 + b) * 1e-3 for b in range(B)]
+
+    def flat(arrs, fill):
+        buf = np.full(B * bstride, fill)
+        for b, arr in enumerate(arrs):
+            buf[b * bstride: b * bstride + ny * ld].reshape(ny, ld)[:, :nx] = arr
+        return buf
+
+    def unflat(buf):
+        return [buf[b * bstride: b * bstride + ny * ld].reshape(ny, ld)[:, :nx] for b in range(B)]
+
+    A = np.full((ny + 2, lda), np.nan)
+    A[:, :nx + 2] = a
+    dA, dU, dDL = dev(A), dev(flat(u, np.nan)), dev(flat(dl, np.nan))
+    LAM = dev(flat(lam0, -7.0))
+    G = dev(np.full((ny + 2, ldg), -9.0))
+    kw = dict(tile=(32, 16), s=5, overlap=(8, 6))
+    tol, cycles = (0.0, 7) if mode == "fixed" else (1e-9, 1_000_000)
+
+    pr = hj.VCProblem()
+    pr.nx, pr.ny, pr.ld, pr.lda, pr.hx, pr.hy = nx, ny, ld, lda, hx, hy
+    pr.a, pr.batch, pr.flags, pr.batch_stride = dA.data_ptr(), B, 0, bstride
+    d = hj.AdjointDesc()
+    d.prob = pr
+    d.u, d.dl_du, d.lam, d.dl_da, d.ld_grad = dU.data_ptr(), dDL.data_ptr(), LAM.data_ptr(), G.data_ptr(), ldg
+    d.params = hj.make_params(kw["tile"], kw["s"], "hierarchical", tol, cycles, 0, kw["overlap"])
+    infos = (hj._Info * B)()
+    torch.cuda.synchronize()
+    st = hj.load().hj_solve_adjoint(ctypes.byref(d), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                    infos)
+    assert st == hj.HJ_OK, hj.last_error()
+    lam_buf = host(LAM)
+    lams = unflat(lam_buf)
+    for b in range(B):
+        xo, co, relo, _ = orc.vc_solve_2d(a, dl[b], lam0[b], hx, hy, tile=kw["tile"], s=kw["s"],
+                                          overlap=kw["overlap"], tol=tol, max_cycles=cycles)
+        say(f"adjoint {mode} b={b}: gpu cycles {infos[b].cycles}, oracle {co}")
+        assert np.array_equal(lams[b], xo), f"batch {b}"
+        if mode == "tol":
+            assert infos[b].cycles == co and abs(infos[b].rel_residual - relo) <= 1e-9 * relo
+    # padding of lam untouched
+    mask = np.ones(B * bstride, bool)
+    for b in range(B):
+        mask[b * bstride: b * bstride + ny * ld].reshape(ny, ld)[:, :nx] = False
+    assert np.all(lam_buf[mask] == -7.0)
+    g = host(G)
+    want = sum(orc.vc_grad_a_2d(u[b], lams[b], hx, hy) for b in range(B))
+    assert np.all(g[:, nx + 2:] == -9.0)
+    assert np.max(np.abs(g[:, :nx + 2] - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_solve_adjoint_binding_without_gradient(orc, prob):
+    """The binding's solve_adjoint with grad_a=False passes NULL dl_da: lam is
+    the adjoint solve alone and no gradient is formed."""
+    nx, ny, hx, hy, a, f = prob
+    Lam = torch.zeros_like(dev(f))
+    infos, g = hj.solve_adjoint(dev(a), None, dev(f), Lam, hx=hx, hy=hy, tile=(32, 32), s=8, overlap=(14, 14),
+                                rel_tol=0.0, max_cycles=4, grad_a=False)
+    assert g is None and len(infos) == f.shape[0]
+    for b in range(f.shape[0]):
+        want = orc.vc_solve_2d(a, f[b], np.zeros((ny, nx)), hx, hy, tile=(32, 32), s=8, overlap=(14, 14),
+                               tol=0.0, max_cycles=4)[0]
+        assert np.array_equal(host(Lam)[b], want)

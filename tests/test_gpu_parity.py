@@ -51,10 +51,11 @@ def gpu_cycles_2d(f, x0, h, tile, s, ncyc, overlap=(0, 0), dtype=torch.float64, 
     return host(X), info
 
 
-def gpu_cycles_1d(f, x0, h, tile, s, ncyc, overlap=0, dtype=torch.float64, method="hierarchical"):
+def gpu_cycles_1d(f, x0, h, tile, s, ncyc, overlap=0, dtype=torch.float64, method="hierarchical",
+                  launch_per_cycle=False):
     F, X = dev(f, dtype), dev(x0, dtype)
     info = hj.solve_1d(F, X, h, tile=tile, s=s, overlap=overlap, method=method, rel_tol=0.0,
-                       max_cycles=ncyc)
+                       max_cycles=ncyc, launch_per_cycle=launch_per_cycle)
     assert info.cycles == ncyc
     return host(X), info
 
@@ -236,13 +237,16 @@ def test_cycle1d_matches_oracle(orc, n, tile, overlap):
         assert np.array_equal(got, orc.hier_1d(f, x0, h, tile, s, nc, overlap))
 
 
-@pytest.mark.parametrize("n", [256, 1, 2, 1025, 100000])
-def test_global_sweep_1d_matches_oracle(orc, n):
+@pytest.mark.parametrize("n", [256, 1, 2, 1025, 6144, 100000])
+@pytest.mark.parametrize("per_sweep", [False, True])
+def test_global_sweep_1d_matches_oracle(orc, n, per_sweep):
+    """Classical sweeps: launch-free in one workgroup where the grid fits
+    (n <= 6144 here), one launch per sweep otherwise or on request."""
     f = W.rhs_random(n, 3)
     x0 = W.rhs_random(n, 4)
     h = 1.0 / (n + 1)
     for nc in (1, 10):
-        got, _ = gpu_cycles_1d(f, x0, h, 32, 1, nc, method="global")
+        got, _ = gpu_cycles_1d(f, x0, h, 32, 1, nc, method="global", launch_per_cycle=per_sweep)
         assert np.array_equal(got, orc.jacobi_1d(f, x0, h, nc))
 
 
@@ -279,10 +283,11 @@ def test_residual_1d_matches_oracle(orc):
 def test_solve_1d_cycles_to_tol_match_oracle(orc, seed):
     f, h = W.make("poisson1d_n256", seed)
     x0 = np.zeros_like(f)
-    for method, om in (("hierarchical", orc.HIERARCHICAL), ("global", orc.CLASSICAL)):
-        say(f"solve1d n=256 seed={seed} {method}")
+    for method, om, lpc in (("hierarchical", orc.HIERARCHICAL, False), ("global", orc.CLASSICAL, False),
+                            ("global", orc.CLASSICAL, True)):
+        say(f"solve1d n=256 seed={seed} {method} launch_per_sweep={lpc}")
         X = dev(x0)
-        info = hj.solve_1d(dev(f), X, h, tile=32, s=16, method=method, rel_tol=1e-6)
+        info = hj.solve_1d(dev(f), X, h, tile=32, s=16, method=method, rel_tol=1e-6, launch_per_cycle=lpc)
         xo, co, relo, r0o = orc.solve_1d(f, x0, h, method=om, tile=32, s=16, tol=1e-6)
         assert info.cycles == co
         assert np.array_equal(host(X), xo)
