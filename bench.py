@@ -549,7 +549,8 @@ def replica_rows(torch, hj, stream):
         ms, infos = timed(lambda: hj.solve_batched(table, rel_tol=1e-4, max_cycles=1_000_000, **kw))
         r1[name] = {"ms": round(ms, 1), "cycles": infos[0].cycles, "sweeps": infos[0].sweeps,
                     "all_copies_same_cycles": all(i.cycles == infos[0].cycles for i in infos)}
-        if name == "overlap_t256_s32_o62":
+        # each one-workgroup row against the per-step run of the same cycle shape
+        if name in ("global", "overlap_t256_s32_o62"):
             x_steps = xs[0].clone()
         elif name.endswith("one_workgroup"):
             r1[name]["iterate_equals_per_step_run"] = bool(torch.equal(xs[0], x_steps))
