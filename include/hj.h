@@ -147,6 +147,26 @@ hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *
 hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
                       const void *f, void *x, const hj_params *p, void *stream, hj_info *info);
 
+/* Allocation-free 2D solve, for callers that cannot allocate device or
+ * pinned memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, validation, iterates, stopping rule,
+ * info and statuses as hj_solve_2d, bit for bit.  It calls no hipMalloc,
+ * hipHostMalloc, hipFree or event creation: its scratch (the control block,
+ * the reduction partials and the two spare iterate arrays, 2 ny ld element
+ * sizes plus a few KB) lives in one static device array of
+ * HJ_NOALLOC_SCRATCH_BYTES in the library, which every device the library
+ * runs on holds until the process ends.  A grid whose scratch exceeds that
+ * size returns HJ_ERR_INVALID_ARG before any HIP call (FP64 grids up to
+ * 2048 x 2048 fit; hj_last_error() states the bytes needed).  In tolerance
+ * mode the host reads the control block after every batch of cycles with a
+ * plain copy and a stream synchronisation (no lookahead).  All calls on one
+ * device share that device's array: calls from several host threads are
+ * serialised, but calls made on one device by other means at the same time
+ * (another process's library instance does not share it) would race on it. */
+#define HJ_NOALLOC_SCRATCH_BYTES (96ull << 20)
+hj_status hj_solve_2d_noalloc(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
+                              const void *f, void *x, const hj_params *p, void *stream, hj_info *info);
+
 /* Mixed precision 2D solve: FP32 hierarchical cycles inside FP64 iterative
  * refinement.  f, x: FP64 (x in/out, ld as in hj_solve_2d).
  *

@@ -173,20 +173,41 @@ struct Step {
     int nb_resid;  // workgroups of the residual kernel
 };
 
-hj_status read_ctrl(DevScratch &S, hipStream_t stream, hj::Ctrl &c)
+// Where a solve keeps its device control block and reduction partials, and how
+// the host reads the block: through two pinned slots and events (one batch of
+// lookahead), or, without them (host == nullptr), by a copy into host memory
+// after each batch followed by a stream synchronisation.
+struct Ctl {
+    hj::Ctrl *ctrl;
+    double *partials;  // npart doubles: two halves, by cycle parity
+    int64_t npart;
+    hj::Ctrl *host;    // 2 pinned slots, or nullptr
+    hipEvent_t ev[2];
+};
+
+Ctl ctl_of(DevScratch &S) { return Ctl{S.ctrl, S.partials, S.npart, S.host, {S.ev[0], S.ev[1]}}; }
+
+hj_status read_ctrl(const Ctl &K, hipStream_t stream, hj::Ctrl &c)
 {
-    HJ_HIP(hipMemcpyAsync(&S.host[0], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
-    HJ_HIP(hipStreamSynchronize(stream));
-    c = S.host[0];
+    if (K.host) {
+        HJ_HIP(hipMemcpyAsync(&K.host[0], K.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
+        HJ_HIP(hipStreamSynchronize(stream));
+        c = K.host[0];
+    } else {
+        HJ_HIP(hipMemcpyAsync(&c, K.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
+        HJ_HIP(hipStreamSynchronize(stream));
+    }
     return HJ_OK;
 }
+
+hj_status read_ctrl(DevScratch &S, hipStream_t stream, hj::Ctrl &c) { return read_ctrl(ctl_of(S), stream, c); }
 
 // latest: in tolerance mode, hand back iterate c + 1 instead of the first
 // iterate c that met the tolerance: it is whole (see stopped()) and one cycle
 // further on; callers that only need a good iterate (the refinement phases)
 // take it, info->cycles then counts it.
 hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_params &p, int64_t spc,
-                hipStream_t stream, DevScratch &S, hj_info *info, bool latest = false)
+                hipStream_t stream, const Ctl &S, hj_info *info, bool latest = false)
 {
     void *bufs[3] = {xu, xs, (char *)xs + xbytes};
     double *part[2] = {S.partials, S.partials + S.npart / 2};
@@ -213,7 +234,7 @@ hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_para
         // a batch or two of early-exit launches follow convergence.
         constexpr double kBatchUs = 500.0;
         int64_t batch = p.check_every > 0 ? p.check_every : 4;
-        auto enqueue = [&](int slot) -> hj_status {
+        auto launch_batch = [&]() -> hj_status {
             const int64_t k = std::min<int64_t>(batch, maxc - next);
             for (int64_t i = 0; i < k; ++i) {
                 const int64_t cc = next + i;
@@ -221,32 +242,51 @@ hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_para
                 HJ_HIP(st.cycle(bufs[cc % 3], bufs[(cc + 1) % 3], true, tol, red));
             }
             next += k;
-            S.host[slot].iter = -1;
-            HJ_HIP(hipMemcpyAsync(&S.host[slot], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
-            HJ_HIP(hipEventRecord(S.ev[slot], stream));
             return HJ_OK;
         };
-        if ((r = enqueue(0)) != HJ_OK) return r;
-        int slot = 0;
         auto t_prev = std::chrono::steady_clock::now();
         int64_t iter_prev = 0;
-        for (;;) {
-            const bool more = next < maxc;
-            if (more && (r = enqueue(slot ^ 1)) != HJ_OK) return r;  // keep the GPU fed
-            HJ_HIP(hipEventSynchronize(S.ev[slot]));
-            if (S.host[slot].status != hj::ST_RUNNING || !more) break;
-            if (p.check_every == 0) {
-                const auto t_now = std::chrono::steady_clock::now();
-                const int64_t done = S.host[slot].iter - iter_prev;
-                const double us = std::chrono::duration<double, std::micro>(t_now - t_prev).count();
-                if (done > 0 && us > 0.0) {
-                    const double per = us / (double)done;
-                    batch = std::max<int64_t>(4, std::min<int64_t>(256, (int64_t)(kBatchUs / per)));
-                }
-                t_prev = t_now;
-                iter_prev = S.host[slot].iter;
+        auto adapt = [&](int64_t iter_now) {
+            if (p.check_every != 0) return;
+            const auto t_now = std::chrono::steady_clock::now();
+            const int64_t done = iter_now - iter_prev;
+            const double us = std::chrono::duration<double, std::micro>(t_now - t_prev).count();
+            if (done > 0 && us > 0.0) {
+                const double per = us / (double)done;
+                batch = std::max<int64_t>(4, std::min<int64_t>(256, (int64_t)(kBatchUs / per)));
             }
-            slot ^= 1;
+            t_prev = t_now;
+            iter_prev = iter_now;
+        };
+        if (S.host) {
+            // one batch of lookahead: the next batch is enqueued before the
+            // host waits for the control block copied after the current one
+            auto enqueue = [&](int slot) -> hj_status {
+                hj_status e;
+                if ((e = launch_batch()) != HJ_OK) return e;
+                S.host[slot].iter = -1;
+                HJ_HIP(hipMemcpyAsync(&S.host[slot], S.ctrl, sizeof(hj::Ctrl), hipMemcpyDeviceToHost, stream));
+                HJ_HIP(hipEventRecord(S.ev[slot], stream));
+                return HJ_OK;
+            };
+            if ((r = enqueue(0)) != HJ_OK) return r;
+            int slot = 0;
+            for (;;) {
+                const bool more = next < maxc;
+                if (more && (r = enqueue(slot ^ 1)) != HJ_OK) return r;  // keep the GPU fed
+                HJ_HIP(hipEventSynchronize(S.ev[slot]));
+                if (S.host[slot].status != hj::ST_RUNNING || !more) break;
+                adapt(S.host[slot].iter);
+                slot ^= 1;
+            }
+        } else {
+            // no pinned slots or events: the stream drains after every batch
+            for (;;) {
+                if ((r = launch_batch()) != HJ_OK) return r;
+                if ((r = read_ctrl(S, stream, c)) != HJ_OK) return r;
+                if (c.status != hj::ST_RUNNING || next >= maxc) break;
+                adapt(c.iter);
+            }
         }
         if ((r = read_ctrl(S, stream, c)) != HJ_OK) return r;
         if (c.status == hj::ST_RUNNING) {
@@ -378,7 +418,7 @@ hj_status solve_vc_locked(const hj_vc_problem &pr, const double *f, double *u, c
             return hipMemcpy2DAsync(dst, (size_t)pr.ld * 8, src, (size_t)pr.ld * 8, (size_t)pr.nx * 8,
                                     (size_t)pr.ny, hipMemcpyDeviceToDevice, st);
         };
-        const hj_status sb = drive(step, ub, S.xbuf, xbytes, P, hier ? P.s : 1, st, S,
+        const hj_status sb = drive(step, ub, S.xbuf, xbytes, P, hier ? P.s : 1, st, ctl_of(S),
                                    infos ? &infos[b] : nullptr);
         if (sb == HJ_ERR_HIP || sb == HJ_ERR_INVALID_ARG) return sb;
         if (sb != HJ_OK && worst == HJ_OK) worst = sb;
@@ -848,6 +888,91 @@ hj_status solve_vc_batched(const hj_vc_problem &pr, const double *f, double *u, 
     return HJ_OK;
 }
 
+// Arguments of a 2D solve, checked before any HIP call.
+hj_status check_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
+                         const void *f, const void *x, const hj_params *p)
+{
+    if (nx < 1 || ny < 1 || nx > kMaxAxis || ny > kMaxAxis)
+        return fail(HJ_ERR_INVALID_ARG, "nx, ny must be in [1, 2^30]");
+    if (ld < nx) return fail(HJ_ERR_INVALID_ARG, "ld must be >= nx");
+    if (!finite_pos(hx) || !finite_pos(hy)) return fail(HJ_ERR_INVALID_ARG, "hx, hy must be finite and > 0");
+    if (dtype != HJ_F64 && dtype != HJ_F32) return fail(HJ_ERR_INVALID_ARG, "unknown dtype");
+    hj_status r;
+    if ((r = check_ptr_dtype(f, dtype, "f", false)) != HJ_OK) return r;
+    if ((r = check_ptr_dtype(x, dtype, "x", false)) != HJ_OK) return r;
+    if ((r = check_params(p, 2)) != HJ_OK) return r;
+    if (p->method == HJ_HIERARCHICAL && !hj::cycle2d_runnable(make_geom2(nx, ny, ld, hx, hy, *p)))
+        return fail(HJ_ERR_UNSUPPORTED, kNeedFullTile);
+    return HJ_OK;
+}
+
+// The current device, and f and x living on it.
+hj_status solve_device(const void *f, const void *x, int &dev)
+{
+    HJ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
+    hj_status r;
+    if ((r = check_device_ptr(f, dev, "f")) != HJ_OK) return r;
+    return check_device_ptr(x, dev, "x");
+}
+
+// One 2D solve on scratch the caller has set up: the two spare iterate arrays
+// at xs (2 xbytes) and the control block and partials in K.
+hj_status solve_2d_on(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
+                      const void *f, void *x, const hj_params &P, hipStream_t st, void *xs,
+                      const Ctl &K, hj_info *info)
+{
+    const hj::Geom2 g = make_geom2(nx, ny, ld, hx, hy, P);
+    const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
+    const size_t es = esize(dtype);
+    const bool hier = P.method == HJ_HIERARCHICAL;
+    const size_t xbytes = (size_t)ny * (size_t)ld * es;
+    Step step;
+    step.nb_cycle = (int)(hier ? hj::cycle2d_blocks(g) : hj::sweep2d_blocks(g));
+    step.nb_resid = (int)hj::resid2d_blocks(g);
+    step.cycle = [&](const void *xi, void *xo, bool res, double tol, const hj::Red &red) {
+        return hier ? hj::launch_cycle2d(dt, g, P.s, res, f, xi, xo, red, tol, st)
+                    : hj::launch_sweep2d(dt, g, res, f, xi, xo, red, tol, st);
+    };
+    step.resid = [&](const void *xi, double *part) {
+        return hj::launch_resid2d(dt, g, f, xi, nullptr, part, st);
+    };
+    step.copy = [&](void *dst, const void *src) {
+        return hipMemcpy2DAsync(dst, (size_t)ld * es, src, (size_t)ld * es, (size_t)nx * es,
+                                (size_t)ny, hipMemcpyDeviceToDevice, st);
+    };
+    return drive(step, x, xs, xbytes, P, hier ? P.s : 1, st, K, info);
+}
+
+// Partials (two halves) a 2D solve needs: one per workgroup of its widest kernel.
+hj_status solve_2d_partials(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, const hj_params &P,
+                            int64_t &npart)
+{
+    const hj::Geom2 g = make_geom2(nx, ny, ld, hx, hy, P);
+    const int64_t nbc = P.method == HJ_HIERARCHICAL ? hj::cycle2d_blocks(g) : hj::sweep2d_blocks(g);
+    const int64_t nbr = hj::resid2d_blocks(g);
+    if (nbc > INT32_MAX || nbr > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "grid too large");
+    npart = 2 * std::max(nbc, nbr);
+    return HJ_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free 2D solve
+// The scratch of hj_solve_2d_noalloc: the control block, the partials and the
+// two spare iterate arrays, carved from one array in the library's own code
+// object.  Each device holds its own copy; its address comes from
+// hipGetSymbolAddress on the first call on that device (in host code the
+// name `scratch` is not a device address).
+constexpr size_t kNoAllocBytes = (size_t)HJ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct NoAllocScratch {
+    std::mutex mu;
+    unsigned char *ptr = nullptr;  // device address of `scratch` on this device
+};
+NoAllocScratch g_noalloc[kMaxDev];
+
+constexpr size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 }  // namespace
 
 extern "C" {
@@ -869,54 +994,55 @@ hj_status hj_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, 
                       const void *f, void *x, const hj_params *p, void *stream, hj_info *info)
 {
     g_err.clear();
-    if (nx < 1 || ny < 1 || nx > kMaxAxis || ny > kMaxAxis)
-        return fail(HJ_ERR_INVALID_ARG, "nx, ny must be in [1, 2^30]");
-    if (ld < nx) return fail(HJ_ERR_INVALID_ARG, "ld must be >= nx");
-    if (!finite_pos(hx) || !finite_pos(hy)) return fail(HJ_ERR_INVALID_ARG, "hx, hy must be finite and > 0");
-    if (dtype != HJ_F64 && dtype != HJ_F32) return fail(HJ_ERR_INVALID_ARG, "unknown dtype");
     hj_status r;
-    if ((r = check_ptr_dtype(f, dtype, "f", false)) != HJ_OK) return r;
-    if ((r = check_ptr_dtype(x, dtype, "x", false)) != HJ_OK) return r;
-    if ((r = check_params(p, 2)) != HJ_OK) return r;
-    if (p->method == HJ_HIERARCHICAL && !hj::cycle2d_runnable(make_geom2(nx, ny, ld, hx, hy, *p)))
-        return fail(HJ_ERR_UNSUPPORTED, kNeedFullTile);
-
+    if ((r = check_solve_2d(nx, ny, ld, hx, hy, dtype, f, x, p)) != HJ_OK) return r;
+    int64_t npart = 0;
+    if ((r = solve_2d_partials(nx, ny, ld, hx, hy, *p, npart)) != HJ_OK) return r;
     int dev = 0;
-    HJ_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= kMaxDev) return fail(HJ_ERR_UNSUPPORTED, "device index out of range");
-    if ((r = check_device_ptr(f, dev, "f")) != HJ_OK) return r;
-    if ((r = check_device_ptr(x, dev, "x")) != HJ_OK) return r;
+    if ((r = solve_device(f, x, dev)) != HJ_OK) return r;
 
     DevScratch &S = g_scr[dev];
     std::lock_guard<std::mutex> lock(S.mu);
-    const hj_params P = *p;
-    const hj::Geom2 g = make_geom2(nx, ny, ld, hx, hy, P);
-    const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
-    const size_t es = esize(dtype);
-    const bool hier = P.method == HJ_HIERARCHICAL;
-    const int64_t nbc = hier ? hj::cycle2d_blocks(g) : hj::sweep2d_blocks(g);
-    const int64_t nbr = hj::resid2d_blocks(g);
-    if (nbc > INT32_MAX || nbr > INT32_MAX) return fail(HJ_ERR_UNSUPPORTED, "grid too large");
-    const size_t xbytes = (size_t)ny * (size_t)ld * es;
-    if ((r = scratch_ensure(S, 2 * xbytes, 2 * std::max(nbc, nbr))) != HJ_OK) return r;
-    hipStream_t st = (hipStream_t)stream;
-
-    Step step;
-    step.nb_cycle = (int)nbc;
-    step.nb_resid = (int)nbr;
-    step.cycle = [&](const void *xi, void *xo, bool res, double tol, const hj::Red &red) {
-        return hier ? hj::launch_cycle2d(dt, g, P.s, res, f, xi, xo, red, tol, st)
-                    : hj::launch_sweep2d(dt, g, res, f, xi, xo, red, tol, st);
-    };
-    step.resid = [&](const void *xi, double *part) {
-        return hj::launch_resid2d(dt, g, f, xi, nullptr, part, st);
-    };
-    step.copy = [&](void *dst, const void *src) {
-        return hipMemcpy2DAsync(dst, (size_t)ld * es, src, (size_t)ld * es, (size_t)nx * es,
-                                (size_t)ny, hipMemcpyDeviceToDevice, st);
-    };
-    return drive(step, x, S.xbuf, xbytes, P, hier ? P.s : 1, st, S, info);
+    const size_t xbytes = (size_t)ny * (size_t)ld * esize(dtype);
+    if ((r = scratch_ensure(S, 2 * xbytes, npart)) != HJ_OK) return r;
+    return solve_2d_on(nx, ny, ld, hx, hy, dtype, f, x, *p, (hipStream_t)stream, S.xbuf, ctl_of(S), info);
 }
+
+hj_status hj_solve_2d_noalloc(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
+                              const void *f, void *x, const hj_params *p, void *stream, hj_info *info)
+{
+    g_err.clear();
+    hj_status r;
+    if ((r = check_solve_2d(nx, ny, ld, hx, hy, dtype, f, x, p)) != HJ_OK) return r;
+    int64_t npart = 0;
+    if ((r = solve_2d_partials(nx, ny, ld, hx, hy, *p, npart)) != HJ_OK) return r;
+    const size_t xbytes = (size_t)ny * (size_t)ld * esize(dtype);
+    const size_t off_part = round256(sizeof(hj::Ctrl));
+    const size_t off_x = off_part + round256((size_t)npart * sizeof(double));
+    const size_t need = off_x + 2 * xbytes;
+    if (need > kNoAllocBytes) {
+        char msg[256];
+        std::snprintf(msg, sizeof msg,
+                      "grid needs %zu bytes of scratch (two iterate arrays of ny * ld elements and "
+                      "%lld partials); hj_solve_2d_noalloc holds at most %zu",
+                      need, (long long)npart, kNoAllocBytes);
+        return fail(HJ_ERR_INVALID_ARG, msg);
+    }
+    int dev = 0;
+    if ((r = solve_device(f, x, dev)) != HJ_OK) return r;
+
+    NoAllocScratch &N = g_noalloc[dev];
+    std::lock_guard<std::mutex> lock(N.mu);
+    if (!N.ptr) {
+        void *a = nullptr;
+        HJ_HIP(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+        if (!a) return fail(HJ_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        N.ptr = (unsigned char *)a;
+    }
+    const Ctl K{(hj::Ctrl *)N.ptr, (double *)(N.ptr + off_part), npart, nullptr, {nullptr, nullptr}};
+    return solve_2d_on(nx, ny, ld, hx, hy, dtype, f, x, *p, (hipStream_t)stream, N.ptr + off_x, K, info);
+}
+
 
 hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, double hy,
                               const double *f, double *x, const hj_refine_params *p,
@@ -1021,7 +1147,7 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
         hj_params P64 = P;
         P64.rel_tol = std::max(sw, p->rel_tol);
         hj_info i64{};
-        const hj_status s1 = drive(s64, x, S.xbuf, b64, P64, hier ? P.s : 1, st, S, &i64, true);
+        const hj_status s1 = drive(s64, x, S.xbuf, b64, P64, hier ? P.s : 1, st, ctl_of(S), &i64, true);
         if (s1 != HJ_OK && s1 != HJ_ERR_NOT_CONVERGED) return s1;
         fp64_cycles = i64.cycles;
         r0_phase1 = i64.r0_norm;
@@ -1041,7 +1167,7 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
         hj_params Pk = P;
         Pk.rel_tol = std::max(P.rel_tol, 0.5 * p->rel_tol * r0_norm / rk_norm);
         hj_info ii{};
-        const hj_status si = drive(step, e32, S.xbuf, b32, Pk, hier ? P.s : 1, st, S, &ii, true);
+        const hj_status si = drive(step, e32, S.xbuf, b32, Pk, hier ? P.s : 1, st, ctl_of(S), &ii, true);
         if (si != HJ_OK && si != HJ_ERR_NOT_CONVERGED) return si;
         inner_cycles += ii.cycles;
         HJ_HIP(hj::launch_axpy_f32_to_f64(g, e32, x, st));
@@ -1067,9 +1193,9 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
 // The whole 1D solve in one workgroup: cycles run in chunks of kWgChunk per
 // launch (a few ms of GPU time), the solve state carried in S.ctrl.  Same stop
 // rule, iterates and info as drive().
-constexpr int64_t kWgChunk = 4096;
+static constexpr int64_t kWgChunk = 4096;
 
-hj_status drive_1d_wg(const hj::Geom1 &g, int dt, const hj_params &p, const void *f, void *x, hipStream_t st,
+static hj_status drive_1d_wg(const hj::Geom1 &g, int dt, const hj_params &p, const void *f, void *x, hipStream_t st,
                       DevScratch &S, hj_info *info)
 {
     const int64_t maxc = p.max_cycles;
@@ -1168,7 +1294,7 @@ hj_status hj_solve_1d(int64_t n, double h, hj_dtype dtype, const void *f, void *
     step.copy = [&](void *dst, const void *src) {
         return hipMemcpyAsync(dst, src, (size_t)n * es, hipMemcpyDeviceToDevice, st);
     };
-    return drive(step, x, S.xbuf, xbytes, P, hier ? P.s : 1, st, S, info);
+    return drive(step, x, S.xbuf, xbytes, P, hier ? P.s : 1, st, ctl_of(S), info);
 }
 
 hj_status hj_residual(int32_t dim, int64_t nx, int64_t ny, int64_t ld, double hx, double hy,
@@ -1277,7 +1403,7 @@ hj_status hj_autotune_batch(const hj_problem *probs, int64_t nprob, hj_dtype dty
 // body of hj_solve_1d); cycles in launches of kWgChunk, the per-problem
 // states read back between launches in tolerance mode.  Called with the
 // device's scratch lock held, problems already checked.
-hj_status solve_batched_wg1d(const hj_problem *probs, int64_t nprob, const hj_batch_params &p, hj_dtype dtype,
+static hj_status solve_batched_wg1d(const hj_problem *probs, int64_t nprob, const hj_batch_params &p, hj_dtype dtype,
                              hipStream_t st, BatchScratch &B, hj_info *infos)
 {
     const hj_params &P1 = p.p1;

@@ -114,7 +114,8 @@ class HJError(RuntimeError):
 
 
 _lib = None
-EXPORTS = ("hj_params_default", "hj_solve_1d", "hj_solve_2d", "hj_solve_2d_refined", "hj_residual",
+EXPORTS = ("hj_params_default", "hj_solve_1d", "hj_solve_2d", "hj_solve_2d_noalloc", "hj_solve_2d_refined",
+           "hj_residual",
            "hj_solve_batched", "hj_autotune", "hj_autotune_batch", "hj_solve_vc_2d", "hj_vc_grad_a", "hj_solve_adjoint",
            "hj_axis_tiles",
            "hj_status_string", "hj_last_error", "hj_version")
@@ -136,6 +137,8 @@ def load():
     lib.hj_solve_1d.restype = i32
     lib.hj_solve_2d.argtypes = [i64, i64, i64, f64, f64, i32, vp, vp, P, vp, I]
     lib.hj_solve_2d.restype = i32
+    lib.hj_solve_2d_noalloc.argtypes = [i64, i64, i64, f64, f64, i32, vp, vp, P, vp, I]
+    lib.hj_solve_2d_noalloc.restype = i32
     lib.hj_solve_2d_refined.argtypes = [i64, i64, i64, f64, f64, vp, vp, ctypes.POINTER(RefineParams),
                                         vp, ctypes.POINTER(_RefineInfo)]
     lib.hj_solve_2d_refined.restype = i32
@@ -265,6 +268,30 @@ def solve_2d(f, x, h=None, *, hx=None, hy=None, tile=(32, 32), s=16, method="hie
     with _device(f):
         st = load().hj_solve_2d(nx, ny, ld, float(hx), float(hy), _dtype_code(f), f.data_ptr(),
                                 x.data_ptr(), ctypes.byref(p), _stream(f), ctypes.byref(info))
+    return _raise_or_info(st, info, allow_not_converged)
+
+
+NOALLOC_SCRATCH_BYTES = 96 << 20  # HJ_NOALLOC_SCRATCH_BYTES
+
+
+def solve_2d_noalloc(f, x, h=None, *, hx=None, hy=None, tile=(32, 32), s=16, method="hierarchical",
+                     rel_tol=1e-6, max_cycles=1_000_000, check_every=0, overlap=(0, 0),
+                     allow_not_converged=False, lds_kernel=False) -> Info:
+    """solve_2d without any allocation inside the library (hj_solve_2d_noalloc):
+    its scratch is a fixed static device array of NOALLOC_SCRATCH_BYTES; larger
+    grids raise HJError (HJ_ERR_INVALID_ARG).  Same iterates and info as solve_2d."""
+    _check_pair(f, x)
+    hx = hx if hx is not None else h
+    hy = hy if hy is not None else hx
+    ld = _ld(f)
+    if _ld(x) != ld:
+        raise ValueError("f and x must share the row stride")
+    ny, nx = f.shape
+    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap, lds_kernel)
+    info = _Info()
+    with _device(f):
+        st = load().hj_solve_2d_noalloc(nx, ny, ld, float(hx), float(hy), _dtype_code(f), f.data_ptr(),
+                                        x.data_ptr(), ctypes.byref(p), _stream(f), ctypes.byref(info))
     return _raise_or_info(st, info, allow_not_converged)
 
 

@@ -66,13 +66,28 @@ FAKE = 0x10000  # aligned non-NULL pointer; validation must reject before it is 
     ((200, 100, 200, 0.1, 0.1, 0), {"tile_x": 64, "tile_y": 128}, hj.HJ_ERR_UNSUPPORTED),
     ((256, 256, 256, 0.1, 0.1, 0), {"tile_x": 128, "tile_y": 128, "flags": 1}, hj.HJ_ERR_UNSUPPORTED),
 ])
-def test_solve_2d_rejects_invalid_arguments(args, kw, code):
+@pytest.mark.parametrize("entry", ["hj_solve_2d", "hj_solve_2d_noalloc"])
+def test_solve_2d_rejects_invalid_arguments(args, kw, code, entry):
     lib = hj.load()
     info = hj._Info()
     p = _params(**kw)
-    st = lib.hj_solve_2d(*args, FAKE, FAKE, ctypes.byref(p), None, ctypes.byref(info))
+    st = getattr(lib, entry)(*args, FAKE, FAKE, ctypes.byref(p), None, ctypes.byref(info))
     assert st == code, hj.last_error()
     assert hj.last_error()
+
+
+@pytest.mark.parametrize("nx,ny,ld,dtype", [(4096, 2048, 4096, hj.HJ_F64), (3072, 2048, 3072, hj.HJ_F64),
+                                            (2048, 2048, 3100, hj.HJ_F64), (4096, 4096, 4096, hj.HJ_F32)])
+def test_noalloc_rejects_grids_beyond_its_scratch_before_any_hip_call(nx, ny, ld, dtype):
+    """Two iterate arrays of ny * ld elements plus the partials must fit the
+    static scratch; larger grids fail up front (FAKE pointers are never used)."""
+    lib = hj.load()
+    info = hj._Info()
+    p = _params(tile_x=64, tile_y=64, s=10, overlap_x=18, overlap_y=18)
+    st = lib.hj_solve_2d_noalloc(nx, ny, ld, 0.01, 0.01, dtype, FAKE, FAKE, ctypes.byref(p), None,
+                                 ctypes.byref(info))
+    assert st == hj.HJ_ERR_INVALID_ARG
+    assert "bytes of scratch" in hj.last_error() and str(hj.NOALLOC_SCRATCH_BYTES) in hj.last_error()
 
 
 def test_solve_rejects_null_and_misaligned_pointers():
