@@ -191,19 +191,29 @@ hj_status hj_solve_2d_noalloc(int64_t nx, int64_t ny, int64_t ld, double hx, dou
  * rel_tol.  switch_tol = 0 selects min(1, 1e4 * rel_tol), or min(1, 1e5 *
  * rel_tol) in the exact regime (hierarchical, overlap >= 2s - 2 on both
  * axes, where a cycle is s classical sweeps); switch_tol >= 1 runs FP32 from
- * the start. */
+ * the start.
+ *
+ * Phase 1 runs toward rel_tol itself and hands over at the switch point only
+ * if it took at least switch_min_cycles FP64 cycles to get there (0 = 8):
+ * about as many remain from there to rel_tol, and for fewer the
+ * refinement's extra passes cost more than its FP32 cycles save.  A solve
+ * that does not hand over is hj_solve_2d's FP64 solve to rel_tol, iterate
+ * for iterate, with outer = 0. */
 typedef struct hj_refine_params {
     hj_params inner;     /* cycle shape for both phases; FP32 solve tolerances (inner.rel_tol > 0) */
     double rel_tol;      /* > 0: outer tolerance on ||f - A x||_2 / ||f - A x_0||_2 */
     double switch_tol;   /* >= 0: FP64 phase target (0 = default, see above) */
     int32_t max_outer;   /* >= 1: refinement steps */
     int32_t flags;       /* must be 0 */
+    int32_t switch_min_cycles; /* >= 0: least FP64 cycles to the switch point for a hand-over (0 = 8) */
+    int32_t pad;         /* ignored */
 } hj_refine_params;
 
 typedef struct hj_refine_info {
     int64_t outer;         /* refinement steps taken */
     int64_t inner_cycles;  /* FP32 cycles over all steps (iterates handed over, as above) */
-    int64_t fp64_cycles;   /* FP64 cycles of phase 1 (index of the iterate handed over) */
+    int64_t fp64_cycles;   /* FP64 cycles of phase 1 (index of the iterate handed over, or of
+                              the result when there was no hand-over) */
     double rel_residual;   /* final FP64 relative residual */
     double r0_norm;        /* ||f - A x_0||_2 */
 } hj_refine_info;

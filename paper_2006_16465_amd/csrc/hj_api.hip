@@ -206,14 +206,18 @@ hj_status read_ctrl(DevScratch &S, hipStream_t stream, hj::Ctrl &c) { return rea
 // iterate c that met the tolerance: it is whole (see stopped()) and one cycle
 // further on; callers that only need a good iterate (the refinement phases)
 // take it, info->cycles then counts it.
+// sw_tol >= 0: the solve may end early at the hand-over point of Ctrl
+// (relative residual <= sw_tol reached first at a cycle >= sw_min_c); it
+// then returns HJ_OK with *status_out = ST_SWITCH and iterate c + 1.
 hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_params &p, int64_t spc,
-                hipStream_t stream, const Ctl &S, hj_info *info, bool latest = false)
+                hipStream_t stream, const Ctl &S, hj_info *info, bool latest = false,
+                double sw_tol = -1.0, int64_t sw_min_c = 0, int32_t *status_out = nullptr)
 {
     void *bufs[3] = {xu, xs, (char *)xs + xbytes};
     double *part[2] = {S.partials, S.partials + S.npart / 2};
     const int64_t maxc = p.max_cycles;
     hj_status r;
-    HJ_HIP(hj::launch_ctrl_init(S.ctrl, stream));
+    HJ_HIP(hj::launch_ctrl_init(S.ctrl, stream, p.rel_tol > 0.0 ? sw_tol : -1.0, sw_min_c));
     int64_t final_c = maxc;
     hj::Ctrl c{};
     if (p.rel_tol <= 0.0) {
@@ -297,8 +301,10 @@ hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_para
             if ((r = read_ctrl(S, stream, c)) != HJ_OK) return r;
         }
         final_c = c.status != hj::ST_RUNNING ? c.done_cycle : maxc;
-        if (latest && c.status == hj::ST_CONVERGED) final_c = std::min<int64_t>(c.done_cycle + 1, maxc);
+        if ((latest && c.status == hj::ST_CONVERGED) || c.status == hj::ST_SWITCH)
+            final_c = std::min<int64_t>(c.done_cycle + 1, maxc);
     }
+    if (status_out) *status_out = c.status;
     if (final_c % 3 != 0) {
         HJ_HIP(st.copy(xu, bufs[final_c % 3]));
         HJ_HIP(hipStreamSynchronize(stream));
@@ -311,7 +317,7 @@ hj_status drive(const Step &st, void *xu, void *xs, size_t xbytes, const hj_para
         if (!std::isfinite(c.last_rsq)) info->rel_residual = NAN;
     }
     if (c.status == hj::ST_NONFINITE) return fail(HJ_ERR_NONFINITE, "residual norm became non-finite");
-    if (p.rel_tol > 0.0 && c.status != hj::ST_CONVERGED)
+    if (p.rel_tol > 0.0 && c.status != hj::ST_CONVERGED && c.status != hj::ST_SWITCH)
         return fail(HJ_ERR_NOT_CONVERGED, "max_cycles reached before rel_tol");
     return HJ_OK;
 }
@@ -888,6 +894,10 @@ hj_status solve_vc_batched(const hj_vc_problem &pr, const double *f, double *u, 
     return HJ_OK;
 }
 
+// Least FP64 cycles to the switch point for hj_solve_2d_refined to hand over
+// to FP32 corrections (hj_refine_params.switch_min_cycles = 0).
+constexpr int64_t kSwitchMinCycles = 8;
+
 // Arguments of a 2D solve, checked before any HIP call.
 hj_status check_solve_2d(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
                          const void *f, const void *x, const hj_params *p)
@@ -1058,6 +1068,7 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
     if ((r = check_ptr_dtype(x, HJ_F64, "x", false)) != HJ_OK) return r;
     if (!p) return fail(HJ_ERR_INVALID_ARG, "params is NULL");
     if (p->flags != 0) return fail(HJ_ERR_INVALID_ARG, "refine flags must be 0");
+    if (p->switch_min_cycles < 0) return fail(HJ_ERR_INVALID_ARG, "switch_min_cycles must be >= 0");
     if (!(p->rel_tol > 0.0)) return fail(HJ_ERR_INVALID_ARG, "rel_tol must be > 0");
     if (p->max_outer < 1) return fail(HJ_ERR_INVALID_ARG, "max_outer must be >= 1");
     if (!(p->inner.rel_tol > 0.0)) return fail(HJ_ERR_INVALID_ARG, "inner.rel_tol must be > 0");
@@ -1143,14 +1154,33 @@ hj_status hj_solve_2d_refined(int64_t nx, int64_t ny, int64_t ld, double hx, dou
         return hipMemcpy2DAsync(dst, (size_t)ld * 8, src, (size_t)ld * 8, (size_t)nx * 8,
                                 (size_t)ny, hipMemcpyDeviceToDevice, st);
     };
+    // The hand-over is taken only if the FP64 cycles needed at least
+    // switch_min_cycles to reach the switch point: about as many remain from
+    // there to rel_tol (equal decades on either side in the exact regime), and
+    // below that the refinement's own passes (two residuals, the
+    // accumulation, a cycle handed over per phase) cost more than FP32 cycles
+    // save; such a solve just runs on in FP64 to rel_tol, unchanged.
     if (sw < 1.0) {
         hj_params P64 = P;
-        P64.rel_tol = std::max(sw, p->rel_tol);
+        P64.rel_tol = p->rel_tol;
         hj_info i64{};
-        const hj_status s1 = drive(s64, x, S.xbuf, b64, P64, hier ? P.s : 1, st, ctl_of(S), &i64, true);
+        int32_t st1 = hj::ST_RUNNING;
+        const int64_t kmin = p->switch_min_cycles > 0 ? p->switch_min_cycles : kSwitchMinCycles;
+        const hj_status s1 = drive(s64, x, S.xbuf, b64, P64, hier ? P.s : 1, st, ctl_of(S), &i64, false,
+                                   sw > p->rel_tol ? sw : -1.0, kmin, &st1);
         if (s1 != HJ_OK && s1 != HJ_ERR_NOT_CONVERGED) return s1;
         fp64_cycles = i64.cycles;
         r0_phase1 = i64.r0_norm;
+        if (st1 != hj::ST_SWITCH) {
+            if (info) {
+                info->outer = 0;
+                info->inner_cycles = 0;
+                info->fp64_cycles = fp64_cycles;
+                info->rel_residual = i64.rel_residual;
+                info->r0_norm = i64.r0_norm;
+            }
+            return s1;
+        }
     }
 
     // phase 2: FP32 correction solves inside FP64 refinement.  Relative

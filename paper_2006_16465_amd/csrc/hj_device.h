@@ -17,11 +17,17 @@ struct Ctrl {
     int64_t iter;        // one past the latest judged iterate
     int64_t done_cycle;  // first c that met the tolerance (or went non-finite); -1 otherwise
     int64_t stop_at;     // cycle kernels evaluating iterate k >= stop_at return at once
-    int32_t status;      // 0 running, 1 converged, 2 non-finite, 3 stopped at max_cycles
+    int32_t status;      // 0 running, 1 converged, 2 non-finite, 3 stopped at max_cycles, 4 switch
     int32_t pad;
+    // Optional hand-over point (sw_tol < 0: none).  The first iterate c with
+    // a relative residual <= sw_tol (and above the tolerance) ends the solve
+    // with ST_SWITCH if c >= sw_min_c; otherwise the solve runs on to the
+    // tolerance.  The decision is taken once: sw_tol is set to -1 after it.
+    double sw_tol;
+    int64_t sw_min_c;
 };
 
-enum : int32_t { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NONFINITE = 2, ST_LIMIT = 3 };
+enum : int32_t { ST_RUNNING = 0, ST_CONVERGED = 1, ST_NONFINITE = 2, ST_LIMIT = 3, ST_SWITCH = 4 };
 
 // ---------------------------------------------------------------------------
 // Tile partition along one axis (subdomains of Sec. 3.3, overlap of Sec. 3.5).
@@ -107,6 +113,10 @@ __device__ inline void judge(Ctrl *ctrl, int64_t c, double rsq, double tol)
     int32_t st = ST_RUNNING;
     if (!isfinite(rsq)) st = ST_NONFINITE;
     else if (rel <= tol) st = ST_CONVERGED;
+    else if (ctrl->sw_tol >= 0.0 && rel <= ctrl->sw_tol) {
+        if (c >= ctrl->sw_min_c) st = ST_SWITCH;
+        else ctrl->sw_tol = -1.0;
+    }
     if (st != ST_RUNNING) {
         ctrl->done_cycle = c;
         // workgroups of the judging kernel (it evaluates iterate c + 1) that

@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kNT) void k_sweep1d(Geom1 g, const T *__restrict__ 
     if (RES) post_partial<kNT>(rsq, red.part_cur);
 }
 
-__global__ void k_ctrl_init(Ctrl *ctrl)
+__global__ void k_ctrl_init(Ctrl *ctrl, double sw_tol, int64_t sw_min_c)
 {
     ctrl->r0sq = 0.0;
     ctrl->last_rsq = 0.0;
@@ -253,6 +253,8 @@ __global__ void k_ctrl_init(Ctrl *ctrl)
     ctrl->stop_at = INT64_MAX;
     ctrl->status = ST_RUNNING;
     ctrl->pad = 0;
+    ctrl->sw_tol = sw_tol;
+    ctrl->sw_min_c = sw_min_c;
 }
 
 // Judge iterate c from n partials left by the previous kernel (one workgroup).
@@ -483,9 +485,9 @@ hipError_t launch_judge(const double *part, int n, Ctrl *ctrl, int64_t c, double
     return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(Ctrl *ctrl, hipStream_t st)
+hipError_t launch_ctrl_init(Ctrl *ctrl, hipStream_t st, double sw_tol, int64_t sw_min_c)
 {
-    k_ctrl_init<<<1, 1, 0, st>>>(ctrl);
+    k_ctrl_init<<<1, 1, 0, st>>>(ctrl, sw_tol, sw_min_c);
     return hipGetLastError();
 }
 

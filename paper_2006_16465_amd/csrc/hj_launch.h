@@ -88,7 +88,8 @@ hipError_t launch_solve1d_wg(int dt, const Geom1 &g, int s, const void *f, void 
 // Sum n partials and judge iterate c (one workgroup).
 hipError_t launch_judge(const double *part, int n, Ctrl *ctrl, int64_t c, double tol, hipStream_t st);
 
-hipError_t launch_ctrl_init(Ctrl *ctrl, hipStream_t st);
+// sw_tol >= 0: hand-over point of the solve (see Ctrl)
+hipError_t launch_ctrl_init(Ctrl *ctrl, hipStream_t st, double sw_tol = -1.0, int64_t sw_min_c = 0);
 
 // variable-coefficient diffusion (hj_vc.hip)
 struct GeomVC {

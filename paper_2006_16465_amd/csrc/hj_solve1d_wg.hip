@@ -204,6 +204,8 @@ __global__ void k_ctrl_init_n(Ctrl *ctrls, int64_t n)
     c.stop_at = INT64_MAX;
     c.status = ST_RUNNING;
     c.pad = 0;
+    c.sw_tol = -1.0;
+    c.sw_min_c = 0;
     ctrls[i] = c;
 }
 

@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
 
 class RefineParams(ctypes.Structure):
     _fields_ = [("inner", Params), ("rel_tol", ctypes.c_double), ("switch_tol", ctypes.c_double),
-                ("max_outer", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("switch_min_cycles", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class _RefineInfo(ctypes.Structure):
@@ -297,12 +298,14 @@ def solve_2d_noalloc(f, x, h=None, *, hx=None, hy=None, tile=(32, 32), s=16, met
 
 def solve_2d_refined(f, x, h=None, *, hx=None, hy=None, tile=(64, 32), s=8, overlap=(14, 14),
                      method="hierarchical", rel_tol=1e-10, inner_tol=1e-6, switch_tol=0.0,
-                     inner_max_cycles=100_000, max_outer=50, check_every=0,
+                     inner_max_cycles=100_000, max_outer=50, check_every=0, switch_min_cycles=0,
                      allow_not_converged=False) -> RefineInfo:
     """FP64 solve: FP64 cycles down to switch_tol (0 = 1e4 * rel_tol, or
     1e5 * rel_tol when overlap >= 2s - 2 on both axes), then FP32 cycles inside
-    FP64 iterative refinement (hj_solve_2d_refined).  f and x are FP64 (ny, nx)
-    tensors; x is updated in place."""
+    FP64 iterative refinement (hj_solve_2d_refined); when the FP64 cycles
+    reach switch_tol in fewer than switch_min_cycles (0 = 8) the solve stays
+    FP64 to rel_tol (outer = 0).  f and x are FP64 (ny, nx) tensors; x is
+    updated in place."""
     import torch
     _check_pair(f, x)
     if f.dtype != torch.float64:
@@ -319,6 +322,7 @@ def solve_2d_refined(f, x, h=None, *, hx=None, hy=None, tile=(64, 32), s=8, over
     rp.switch_tol = switch_tol
     rp.max_outer = max_outer
     rp.flags = 0
+    rp.switch_min_cycles = switch_min_cycles
     info = _RefineInfo()
     with _device(f):
         st = load().hj_solve_2d_refined(nx, ny, ld, float(hx), float(hy), f.data_ptr(), x.data_ptr(),

@@ -131,6 +131,8 @@ def test_refined_solve_rejects_invalid_arguments():
     assert call(rp(rel_tol=0.0)) == hj.HJ_ERR_INVALID_ARG
     assert call(rp(max_outer=0)) == hj.HJ_ERR_INVALID_ARG
     assert call(rp(flags=1)) == hj.HJ_ERR_INVALID_ARG
+    assert call(rp(switch_min_cycles=-1)) == hj.HJ_ERR_INVALID_ARG
+    assert ctypes.sizeof(hj.RefineParams) == 80  # hj_refine_params in include/hj.h
     assert call(rp(switch_tol=-1e-3)) == hj.HJ_ERR_INVALID_ARG
     assert call(rp(switch_tol=float("nan"))) == hj.HJ_ERR_INVALID_ARG
     assert call(rp(switch_tol=float("inf"))) == hj.HJ_ERR_INVALID_ARG

@@ -532,6 +532,35 @@ def test_refined_solve_reaches_1e10_and_matches_fp64_oracle(orc, tile, s, ov, se
     assert abs(total - co) <= 2 * info.outer + 4 + co // 25
 
 
+@pytest.mark.parametrize("seed,c1", [(0, 3), (5, 7)])
+def test_refined_solve_stays_fp64_when_the_switch_point_comes_early(orc, seed, c1):
+    """The FP64 cycles reach the switch point (1e5 * rel_tol in the exact
+    regime) in c1 < 8 cycles: no hand-over, the result is hj_solve_2d's FP64
+    solve to rel_tol bit for bit (equal to the oracle's), outer = 0.  With
+    switch_min_cycles = 1 the same problem hands over at cycle c1 and
+    refines."""
+    n = 256
+    f = W.rhs_2d_modes(n, n, 8, 0.0, seed)
+    h = 1.0 / (n + 1)
+    kw = dict(tile=(64, 32), s=8, overlap=(14, 14))
+    _, c1o, _, _ = orc.solve_2d(f, np.zeros_like(f), h, h, tol=1e-5, **kw)
+    assert c1o == c1
+    X = dev(np.zeros_like(f))
+    info = hj.solve_2d_refined(dev(f), X, h, rel_tol=1e-10, inner_tol=1e-6, **kw)
+    Y = dev(np.zeros_like(f))
+    one = hj.solve_2d(dev(f), Y, h, rel_tol=1e-10, **kw)
+    xo, co, _, _ = orc.solve_2d(f, np.zeros_like(f), h, h, tol=1e-10, **kw)
+    say(f"refined seed {seed}: outer {info.outer}, fp64 cycles {info.fp64_cycles} (FP64 solve {one.cycles})")
+    assert info.outer == 0 and info.inner_cycles == 0
+    assert info.fp64_cycles == one.cycles == co
+    assert torch.equal(X, Y) and np.array_equal(host(X), xo)
+    assert info.rel_residual == one.rel_residual
+    X.zero_()
+    forced = hj.solve_2d_refined(dev(f), X, h, rel_tol=1e-10, inner_tol=1e-6, switch_min_cycles=1, **kw)
+    assert forced.outer >= 1 and forced.fp64_cycles == c1 + 1
+    assert fp64_residual_np(f, host(X), h) <= 1.001e-10
+
+
 def test_refined_solve_fp32_from_the_start_still_converges():
     """switch_tol >= 1: refinement alone (no FP64 phase) reaches 1e-10; FP32
     rounding leaves slow-mode error that costs extra cycles, which is why the
