@@ -55,6 +55,12 @@
 
 #ifdef _OPENMP
 #include <omp.h>
+
+/* Loops over fewer point updates than this run on one thread: a parallel
+ * region costs more than such a loop (and far more when several processes
+ * share the cores).  Each point is computed on its own, so the thread count
+ * never changes a result. */
+#define PAR_MIN_POINTS ((int64_t)1 << 16)
 #endif
 
 /* ------------------------------------------------------------------ */
@@ -164,7 +170,7 @@ void orc_jacobi_1d(int64_t n, double h, const double *f, double *x, int64_t nswe
 static void jacobi_sweep_2d(int64_t nx, int64_t ny, const coef2 *c, const double *f,
                             const double *cur, double *nxt)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN_POINTS)
     for (int64_t r = 0; r < ny; ++r) {
         for (int64_t q = 0; q < nx; ++q) {
             double w = q > 0 ? cur[r * nx + q - 1] : 0.0;
@@ -201,7 +207,7 @@ static void hier_cycle_1d(int64_t n, double h, const double *f, const double *xi
     double hh = h * h;
     int64_t nt = orc_axis_ntiles(n, t, o);
     int64_t ext = axis_extent(n, t);
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (nt * ext * s >= PAR_MIN_POINTS)
     for (int64_t ti = 0; ti < nt; ++ti) {
         int64_t x0 = orc_axis_start(n, t, o, ti);
         /* step 1: copy the subdomain plus one point each side into both
@@ -239,7 +245,7 @@ static void hier_cycle_2d(int64_t nx, int64_t ny, const coef2 *c, const double *
     int64_t ntx = orc_axis_ntiles(nx, tx, ox), nty = orc_axis_ntiles(ny, ty, oy);
     int64_t ex = axis_extent(nx, tx), ey = axis_extent(ny, ty);
     int64_t p = ex + 2; /* local pitch */
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (ntx * nty * ex * ey * s >= PAR_MIN_POINTS)
     for (int64_t tid = 0; tid < ntx * nty; ++tid) {
         int64_t bi = tid / ntx, bj = tid % ntx;
         int64_t r0 = orc_axis_start(ny, ty, oy, bi);
@@ -346,7 +352,7 @@ double orc_residual_2d(int64_t nx, int64_t ny, double hx, double hy, const doubl
 {
     double wx = 1.0 / (hx * hx), wy = 1.0 / (hy * hy);
     double *rr = r ? r : (double *)calloc((size_t)(nx * ny), sizeof(double));
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN_POINTS)
     for (int64_t row = 0; row < ny; ++row) {
         for (int64_t q = 0; q < nx; ++q) {
             int64_t a = row * nx + q;
@@ -484,7 +490,7 @@ void orc_vc_apply_2d(int64_t nx, int64_t ny, double hx, double hy, const double 
                      double *out)
 {
     double ihx2 = 1.0 / (hx * hx), ihy2 = 1.0 / (hy * hy);
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN_POINTS)
     for (int64_t r = 0; r < ny; ++r) {
         for (int64_t q = 0; q < nx; ++q) {
             vc_coef k = vc_at(nx, ihx2, ihy2, a, r, q);
@@ -512,7 +518,7 @@ double orc_vc_residual_2d(int64_t nx, int64_t ny, double hx, double hy, const do
 static void vc_jacobi_sweep(int64_t nx, int64_t ny, double ihx2, double ihy2, const double *a,
                             const double *f, const double *cur, double *nxt)
 {
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN_POINTS)
     for (int64_t r = 0; r < ny; ++r) {
         for (int64_t q = 0; q < nx; ++q) {
             vc_coef k = vc_at(nx, ihx2, ihy2, a, r, q);
@@ -533,7 +539,7 @@ static void vc_hier_cycle(int64_t nx, int64_t ny, double ihx2, double ihy2, cons
     int64_t ntx = orc_axis_ntiles(nx, tx, ox), nty = orc_axis_ntiles(ny, ty, oy);
     int64_t ex = axis_extent(nx, tx), ey = axis_extent(ny, ty);
     int64_t p = ex + 2;
-    #pragma omp parallel for schedule(static)
+    #pragma omp parallel for schedule(static) if (ntx * nty * ex * ey * s >= PAR_MIN_POINTS)
     for (int64_t tid = 0; tid < ntx * nty; ++tid) {
         int64_t bi = tid / ntx, bj = tid % ntx;
         int64_t r0 = orc_axis_start(ny, ty, oy, bi);
