@@ -780,6 +780,69 @@ def diffusion_rows(torch, hj, stream):
     out["vc_cycle_1024"] = {"tile": list(shape["tile"]), "s": shape["s"], "overlap": list(shape["overlap"]),
                             "us_per_cycle": round(us, 1), "gsweeps_per_s": round(n * n * shape["s"] / us / 1e3, 1)}
 
+    # the configuration's own size, 16 right-hand sides: measured cycle rate
+    # of the batched forward and adjoint solves and a projection of the time
+    # to 1e-10 from the per-cycle residual factor between cycles c1 and c2
+    log("differentiable: 1024^2 x 16 forward and adjoint, rate-based projection to 1e-10")
+    B, c1, c2 = 16, 500, 1500
+    F16 = torch.from_numpy(np.stack([W.rhs_2d_modes(n, n, 8, 0.0, b) for b in range(B)])).cuda()
+    U16 = torch.zeros_like(F16)
+    T16 = torch.from_numpy(np.stack([W.smooth_modes_2d(n, 3, 3, 100 + b) for b in range(B)]) * 1e-3).cuda()
+
+    def capped(solve, cycles):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        infos = solve(cycles)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1), [i.rel_residual for i in infos]
+
+    def project(solve, what):
+        t1, r1 = capped(solve, c1)
+        t2, r2 = capped(solve, c2)
+        per_cycle_ms = (t2 - t1) / (c2 - c1)
+        proj = []
+        for a1, a2 in zip(r1, r2):
+            if a2 <= 1e-10:
+                proj.append(c2)
+                continue
+            rho = (a2 / a1) ** (1.0 / (c2 - c1))
+            proj.append(float("inf") if rho >= 1.0 else c2 + np.log(1e-10 / a2) / np.log(rho))
+        worst = max(proj)
+        finite = np.isfinite(worst)
+        log(f"differentiable: {what}: rel residuals at {c1}: {r1}; at {c2}: {r2}")
+        return {"batch": B, "cycles_measured": [c1, c2], "ms_per_cycle_batch": round(per_cycle_ms, 3),
+                "gsweeps_per_s": round(B * n * n * shape["s"] / per_cycle_ms / 1e6, 1),
+                "rel_residual_at_c1_max": max(r1), "rel_residual_at_c2_max": max(r2),
+                "per_cycle_factor_worst": max((b2 / b1) ** (1.0 / (c2 - c1)) for b1, b2 in zip(r1, r2)),
+                "projected_cycles_to_1e-10": round(worst) if finite else None,
+                "projected_s_to_1e-10": round(worst * per_cycle_ms * 1e-3, 1) if finite else None,
+                "what": what}
+
+    def fwd(cycles):
+        U16.zero_()
+        return hj.solve_vc_2d(a, F16, U16, h, rel_tol=1e-10, max_cycles=cycles, allow_not_converged=True, **shape)
+
+    out["config_1024x16_forward"] = project(fwd, "forward solve, 16 random-mode right-hand sides")
+    DL16 = 2.0 * (U16 - T16) / U16.numel()
+    L16 = torch.zeros_like(F16)
+
+    def adj(cycles):
+        L16.zero_()
+        return hj.solve_adjoint(a, U16, DL16, L16, h, rel_tol=1e-10, max_cycles=cycles, grad_a=False,
+                                allow_not_converged=True, **shape)[0]
+
+    out["config_1024x16_adjoint"] = project(adj, "adjoint solve, dL/du = 2 (u - t) / N with t smooth")
+    # a smooth right-hand side sits in the slowest modes: with a = 1 the
+    # smoothest Jacobi mode decays by cos(pi h) per sweep, so a cycle of s
+    # exact sweeps gains cos(pi h)^s; the variable coefficient only slows it
+    lb = int(np.ceil(np.log(1e-10) / (shape["s"] * np.log(np.cos(np.pi * h)))))
+    adj_row = out["config_1024x16_adjoint"]
+    adj_row["cycles_to_1e-10_if_a_were_1"] = lb
+    adj_row["s_to_1e-10_if_a_were_1"] = round(lb * adj_row["ms_per_cycle_batch"] * 1e-3, 1)
+    log(f"differentiable: {out['config_1024x16_forward']}; {out['config_1024x16_adjoint']}")
+    del F16, U16, T16, DL16, L16
+
     def pipeline(n, batch, tol, seed):
         h = 1.0 / (n + 1)
         a0 = torch.from_numpy(W.diffusion_coefficient(n, 0.05, 1.0, seed)).cuda()

@@ -228,3 +228,40 @@ def test_solve_adjoint_binding_without_gradient(orc, prob):
         want = orc.vc_solve_2d(a, f[b], np.zeros((ny, nx)), hx, hy, tile=(32, 32), s=8, overlap=(14, 14),
                                tol=0.0, max_cycles=4)[0]
         assert np.array_equal(host(Lam)[b], want)
+
+
+def test_vc_config_size_forward_and_adjoint_match_oracle(orc):
+    """The differentiable configuration at its own size: 1024 x 1024,
+    a = exp(g) (squared-exponential field, length 0.05, variance 1), 16
+    right-hand sides through the batched engine.  Three fixed cycles of the
+    forward solve (64 x 32 tiles, s = 8, overlap 14) equal the oracle's per
+    right-hand side bit for bit; the adjoint solve through hj_solve_adjoint
+    on dL/du = 2 (u - t) / N from those states equals the oracle's solve of
+    the same right-hand sides bit for bit, and dL/da equals the oracle's
+    face-product gradient summed over the batch within 1e-12."""
+    n, B, K = 1024, 16, 3
+    h = 1.0 / (n + 1)
+    kw = dict(tile=(64, 32), s=8, overlap=(14, 14))
+    a = W.diffusion_coefficient(n, 0.05, 1.0, 7)
+    f = np.stack([W.rhs_2d_modes(n, n, 8, 0.0, b) for b in range(B)])
+    A, F = dev(a), dev(f)
+    U = torch.zeros_like(F)
+    hj.solve_vc_2d(A, F, U, h, rel_tol=0.0, max_cycles=K, **kw)
+    u = host(U)
+    for b in range(B):
+        want = orc.vc_solve_2d(a, f[b], np.zeros((n, n)), h, h, tol=0.0, max_cycles=K, **kw)[0]
+        assert np.array_equal(u[b], want), f"forward, right-hand side {b}"
+    t = np.stack([W.smooth_modes_2d(n, 3, 3, 100 + b) for b in range(B)]) * 1e-3
+    dl = 2.0 * (u - t) / u.size
+    LAM = torch.zeros_like(F)
+    infos, G = hj.solve_adjoint(A, U, dev(dl), LAM, h, rel_tol=0.0, max_cycles=K, **kw)
+    lam = host(LAM)
+    assert len(infos) == B and all(i.cycles == K for i in infos)
+    for b in range(B):
+        want = orc.vc_solve_2d(a, dl[b], np.zeros((n, n)), h, h, tol=0.0, max_cycles=K, **kw)[0]
+        assert np.array_equal(lam[b], want), f"adjoint, right-hand side {b}"
+    want_g = sum(orc.vc_grad_a_2d(u[b], lam[b], h, h) for b in range(B))
+    g = host(G)
+    err = np.max(np.abs(g - want_g)) / np.max(np.abs(want_g))
+    say(f"1024^2 x 16: dL/da max difference {err:.2e} of the largest entry")
+    assert err <= 1e-12
