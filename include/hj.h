@@ -74,16 +74,27 @@
 extern "C" {
 #endif
 
+/* The *_RANGE_MIN / *_RANGE_MAX names of the enums below are not values to
+ * pass: they widen each type to the whole int32 range, so that any integer a
+ * caller passes is a valid value of the type (an invalid one is rejected with
+ * HJ_ERR_INVALID_ARG, or named "unknown status"). */
 typedef enum hj_status {
     HJ_OK = 0,
     HJ_ERR_INVALID_ARG = 1,   /* argument validation failed; nothing was run */
     HJ_ERR_NOT_CONVERGED = 2, /* max_cycles reached; x and info hold the last iterate */
     HJ_ERR_NONFINITE = 3,     /* a residual norm became NaN/Inf; x holds that iterate */
     HJ_ERR_UNSUPPORTED = 4,   /* valid but not provided (tile shape, entry point) */
-    HJ_ERR_HIP = 5            /* a HIP runtime call failed; see hj_last_error() */
+    HJ_ERR_HIP = 5,           /* a HIP runtime call failed; see hj_last_error() */
+    HJ_STATUS_RANGE_MIN = -2147483647 - 1,
+    HJ_STATUS_RANGE_MAX = 2147483647
 } hj_status;
 
-typedef enum hj_dtype { HJ_F64 = 0, HJ_F32 = 1 } hj_dtype;
+typedef enum hj_dtype {
+    HJ_F64 = 0,
+    HJ_F32 = 1,
+    HJ_DTYPE_RANGE_MIN = -2147483647 - 1,
+    HJ_DTYPE_RANGE_MAX = 2147483647
+} hj_dtype;
 
 typedef enum hj_method { HJ_HIERARCHICAL = 0, HJ_GLOBAL = 1 } hj_method;
 

@@ -1712,6 +1712,7 @@ const char *hj_status_string(hj_status s)
     case HJ_ERR_NONFINITE: return "HJ_ERR_NONFINITE";
     case HJ_ERR_UNSUPPORTED: return "HJ_ERR_UNSUPPORTED";
     case HJ_ERR_HIP: return "HJ_ERR_HIP";
+    default: break;
     }
     return "HJ_ERR_UNKNOWN";
 }
