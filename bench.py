@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--no-diffusion", action="store_true",
                     help="skip the variable-coefficient / adjoint rows")
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D rows")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="skip the row with the shape hj_autotune_solve picks on an independent seed")
     ap.add_argument("--no-c2", action="store_true",
                     help="skip the 512^2 rows (Sec. 4.2 experiment: 32 x 32 tiles, s in {1, 4, 8, 16, 32})")
     ap.add_argument("--no-replica", action="store_true",
@@ -293,6 +295,25 @@ def main():
             "timing": f"{args.warmup} warmup + {args.steps} timed steps, per-seed medians",
         }
 
+    if not args.no_tuned:
+        # the right-hand-side tuner run on an independent right-hand side of
+        # the same workload (seed 5, not timed here), its shape then solving
+        # seeds 0-4 like the headline
+        log("shape tuned on seed 5 with hj_autotune_solve, applied to the timed seeds")
+        f5 = torch.from_numpy(W.rhs_2d_modes(n, n, 8, 0.0, 5)).to(dev)
+        t0 = time.perf_counter()
+        tt, ts, tov, _ = hj.autotune_solve(f5, None, h, trial_tol=args.tol)
+        tune_s = time.perf_counter() - t0
+        del f5
+        wall_t, per_t = timed("hierarchical", 1, 1, tile=tt, s=ts, ov=tov)
+        extra["tuned_shape"] = {
+            "tile": list(tt), "s": ts, "overlap": list(tov), "tuning_s": round(tune_s, 2),
+            "tuned_on": "seed 5 (hj_autotune_solve, trial solves to the same tolerance, inexact overlaps included)",
+            "ms_per_problem": round(wall_t / nprob, 3),
+            "cycles_per_seed": dict(zip(map(str, args.seeds), [i.cycles for _, i in per_t[0]])),
+            "ms_per_seed": dict(zip(map(str, args.seeds), [round(ms, 3) for ms, _ in per_t[0]])),
+        }
+        log(f"tuned shape: {extra['tuned_shape']}")
     if not args.no_c2:
         extra["poisson2d_512"] = c2_rows(torch, hj, stream)
     if not args.no_mixed:
@@ -730,20 +751,29 @@ def replica_rows(torch, hj, stream):
     X2 = torch.empty_like(F2)
     r2 = {"workload": "2D -lap u = 1 on 1024^2, x0 = 1, to 1e-4"}
     tile2, s2, ov2, _ = hj.autotune(2, n, n)
+    # the right-hand-side tuner: trial solves of this problem to the same
+    # tolerance, inexact overlaps included (its own time is reported apart)
+    X2.fill_(1.0)
+    tune_ms, (tile3, s3, ov3, trial_ms) = timed(lambda: hj.autotune_solve(F2, X2, h, trial_tol=1e-4))
     for name, kw in (("global", dict(method="global")),
                      ("paper_t32x32_s16", dict(tile=(32, 32), s=16, overlap=(0, 0))),
                      ("paper_t32x32_s32_o4", dict(tile=(32, 32), s=32, overlap=(4, 4))),
-                     ("overlap_autotuned", dict(tile=tile2, s=s2, overlap=ov2))):
+                     ("overlap_autotuned_exact_regime", dict(tile=tile2, s=s2, overlap=ov2)),
+                     ("overlap_autotuned", dict(tile=tile3, s=s3, overlap=ov3))):
         X2.fill_(1.0)
         ms, info = timed(lambda: hj.solve_2d(F2, X2, h, rel_tol=1e-4, max_cycles=1_000_000, **kw))
         r2[name] = {"ms": round(ms, 1), "cycles": info.cycles, "sweeps": info.sweeps}
+        if name == "overlap_autotuned_exact_regime":
+            r2[name].update(tile=list(tile2), s=s2, overlap=list(ov2), by="hj_autotune (o = 2s - 2, time per sweep)")
         if name == "overlap_autotuned":
-            r2[name].update(tile=list(tile2), s=s2, overlap=list(ov2))
+            r2[name].update(tile=list(tile3), s=s3, overlap=list(ov3), tuning_ms=round(tune_ms, 1),
+                            by="hj_autotune_solve (trial solves of this problem to 1e-4, inexact overlaps included)")
         log(f"replica R2 {name}: {ms:.1f} ms, {info.cycles} cycles")
     r2["speedup_paper_setting"] = round(r2["global"]["ms"] / r2["paper_t32x32_s16"]["ms"], 2)
     r2["speedup_paper_overlap_setting"] = round(r2["global"]["ms"] / r2["paper_t32x32_s32_o4"]["ms"], 2)
     r2["paper_reported"] = {"t32x32_s16": 3.98, "t32x32_s32_o4": 5.84, "note": "the paper's Tables 3 and 4, its own GPU"}
     r2["speedup_overlap"] = round(r2["global"]["ms"] / r2["overlap_autotuned"]["ms"], 2)
+    r2["speedup_overlap_exact_regime"] = round(r2["global"]["ms"] / r2["overlap_autotuned_exact_regime"]["ms"], 2)
     r2["hbm_pass_ratio_paper_setting"] = round(r2["global"]["cycles"] / r2["paper_t32x32_s16"]["cycles"], 2)
     out["r2_2d_1024"] = r2
     return out

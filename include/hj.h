@@ -321,6 +321,37 @@ hj_status hj_solve_batched(const hj_problem *probs, int64_t nprob, const hj_batc
 hj_status hj_autotune(int32_t dim, int64_t nx, int64_t ny, hj_dtype dtype, void *stream,
                       hj_params *best, double *us_per_sweep);
 
+/* Shape tuning on the caller's own problem.  The exact-regime tuner above
+ * ranks shapes by time per classical sweep; an overlap below 2s - 2 lets
+ * stale halo values reach owned points, which on smooth error still gains
+ * close to s classical sweeps per cycle at a fraction of the redundant work
+ * (Sec. 3.5 Table 2, Sec. 4.3 Table 4), and on other right-hand sides stalls.
+ * This tuner therefore solves the given 2D problem (f, starting from x0,
+ * which is not modified) to trial_tol with each candidate shape and keeps
+ * the one that got there first, by wall time on the stream:
+ *   tiles 32x32, 64x32, 32x64, 64x64, 64x128 that fit the grid (or only
+ *   (tile_x, tile_y) when given), s in {4, 8, 12, 16, 24, 32}, even overlaps
+ *   {0, 2, 4, 8, 2s - 2} below the tile; exact-regime shapes first.
+ * A candidate is skipped without a trial when its measured time per cycle
+ * times ceil(N / s) already exceeds the best time, N being the classical
+ * sweep count the exact-regime trials revealed (a cycle gains at most s
+ * classical sweeps); each trial is capped at the cycles that could still
+ * beat the best, and at max_trial_cycles.  best gets the winner
+ * (hierarchical, rel_tol = trial_tol, other fields defaulted), *best_ms its
+ * time (may be NULL).  HJ_ERR_NOT_CONVERGED if no candidate reached
+ * trial_tol within max_trial_cycles. */
+typedef struct hj_tune_params {
+    double trial_tol;         /* > 0: relative residual each trial solve must reach */
+    int64_t max_trial_cycles; /* >= 1: cap per trial */
+    int32_t tile_x, tile_y;   /* 0, 0: all candidate tiles; else only this tile (a 2D tile shape) */
+    int32_t flags;            /* must be 0 */
+    int32_t pad;
+} hj_tune_params;
+
+hj_status hj_autotune_solve(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
+                            const void *f, const void *x0, const hj_tune_params *tp, void *stream,
+                            hj_params *best, double *best_ms);
+
 /* The cycle shapes hj_solve_batched with HJ_BATCH_AUTOTUNE uses for this
  * table: hj_autotune on the largest 2D problem with tiles no larger than the
  * smallest 2D problem (and tile_x <= 64), and on the largest 1D problem.

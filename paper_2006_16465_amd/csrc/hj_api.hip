@@ -1405,6 +1405,135 @@ hj_status hj_autotune(int32_t dim, int64_t nx, int64_t ny, hj_dtype dtype, void 
     return HJ_OK;
 }
 
+hj_status hj_autotune_solve(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,
+                            const void *f, const void *x0, const hj_tune_params *tp, void *stream,
+                            hj_params *best, double *best_ms)
+{
+    g_err.clear();
+    if (!tp || !best) return fail(HJ_ERR_INVALID_ARG, "tune params and best must not be NULL");
+    if (!(tp->trial_tol > 0.0) || !std::isfinite(tp->trial_tol))
+        return fail(HJ_ERR_INVALID_ARG, "trial_tol must be finite and > 0");
+    if (tp->max_trial_cycles < 1) return fail(HJ_ERR_INVALID_ARG, "max_trial_cycles must be >= 1");
+    if (tp->flags != 0) return fail(HJ_ERR_INVALID_ARG, "tune flags must be 0");
+    if ((tp->tile_x == 0) != (tp->tile_y == 0)) return fail(HJ_ERR_INVALID_ARG, "give both tile extents or neither");
+    if (tp->tile_x && !hj::cycle2d_supported(tp->tile_x, tp->tile_y))
+        return fail(HJ_ERR_UNSUPPORTED, "unsupported 2D tile shape");
+    hj_params base;
+    hj_params_default(&base);
+    base.rel_tol = tp->trial_tol;
+    base.max_cycles = tp->max_trial_cycles;
+    hj_status r;
+    if ((r = check_solve_2d(nx, ny, ld, hx, hy, dtype, f, x0, &base)) != HJ_OK) return r;
+
+    // candidates: exact regime first (they reveal the classical sweep count)
+    std::vector<hj_params> cands;
+    const int tiles[][2] = {{64, 128}, {64, 64}, {32, 64}, {64, 32}, {32, 32}};
+    for (const bool exact : {true, false}) {
+        for (auto &t : tiles) {
+            const int tx = tp->tile_x ? tp->tile_x : t[0], ty = tp->tile_y ? tp->tile_y : t[1];
+            if (tp->tile_x && (t[0] != tiles[0][0] || t[1] != tiles[0][1])) continue;  // the given tile once
+            for (const int s : {32, 24, 16, 12, 8, 4}) {
+                for (const int o : {2 * s - 2, 8, 4, 2, 0}) {
+                    if ((o == 2 * s - 2) != exact || o >= std::min(tx, ty) || o < 0) continue;
+                    if (!exact && o >= 2 * s - 2) continue;
+                    hj_params P = base;
+                    P.tile_x = tx;
+                    P.tile_y = ty;
+                    P.s = s;
+                    P.overlap_x = P.overlap_y = o;
+                    if (!hj::cycle2d_runnable(make_geom2(nx, ny, ld, hx, hy, P))) continue;
+                    bool dup = false;
+                    for (const hj_params &c : cands)
+                        dup = dup || (c.tile_x == P.tile_x && c.tile_y == P.tile_y && c.s == P.s &&
+                                      c.overlap_x == P.overlap_x);
+                    if (!dup) cands.push_back(P);
+                }
+            }
+        }
+    }
+    if (cands.empty()) return fail(HJ_ERR_UNSUPPORTED, "autotune_solve: no candidate tile fits the grid");
+    int64_t npart = 0;
+    for (const hj_params &P : cands) {
+        int64_t np = 0;
+        if ((r = solve_2d_partials(nx, ny, ld, hx, hy, P, np)) != HJ_OK) return r;
+        npart = std::max(npart, np);
+    }
+    int dev = 0;
+    if ((r = solve_device(f, x0, dev)) != HJ_OK) return r;
+    DevScratch &S = g_scr[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    const size_t es = esize(dtype);
+    const size_t xbytes = (size_t)ny * (size_t)ld * es;
+    // the trial iterate, then the solve's two spare arrays
+    if ((r = scratch_ensure(S, 3 * xbytes, npart)) != HJ_OK) return r;
+    if (!S.tev[0]) {
+        HJ_HIP(hipEventCreate(&S.tev[0]));
+        HJ_HIP(hipEventCreate(&S.tev[1]));
+    }
+    hipStream_t st = (hipStream_t)stream;
+    void *xw = S.xbuf;
+    void *xs = (char *)S.xbuf + xbytes;
+    const int dt = dtype == HJ_F64 ? hj::F64 : hj::F32;
+    HJ_HIP(hipMemsetAsync(xs, 0, 2 * xbytes, st));  // the per-cycle timings run on zeros
+    auto restore = [&]() {
+        return hipMemcpy2DAsync(xw, (size_t)ld * es, x0, (size_t)ld * es, (size_t)nx * es, (size_t)ny,
+                                hipMemcpyDeviceToDevice, st);
+    };
+    // time per cycle from a few fixed cycles between the spare arrays
+    auto cycle_ms = [&](const hj_params &P, double &ms) -> hj_status {
+        const hj::Geom2 g = make_geom2(nx, ny, ld, hx, hy, P);
+        const hj::Red none{nullptr, nullptr, S.ctrl, 0, 0};
+        void *a = xs, *b = (char *)xs + xbytes;
+        HJ_HIP(hj::launch_cycle2d(dt, g, P.s, false, f, a, b, none, -1.0, st));
+        constexpr int k = 6;
+        HJ_HIP(hipEventRecord(S.tev[0], st));
+        for (int i = 0; i < k; ++i) HJ_HIP(hj::launch_cycle2d(dt, g, P.s, false, f, (i & 1) ? b : a, (i & 1) ? a : b, none, -1.0, st));
+        HJ_HIP(hipEventRecord(S.tev[1], st));
+        HJ_HIP(hipEventSynchronize(S.tev[1]));
+        float e = 0.0f;
+        HJ_HIP(hipEventElapsedTime(&e, S.tev[0], S.tev[1]));
+        ms = (double)e / k;
+        return HJ_OK;
+    };
+    double best_t = INFINITY;
+    int64_t n_classical = 0;  // lower bound on the classical sweep count to trial_tol
+    hj_params winner = cands[0];
+    for (const hj_params &P0 : cands) {
+        double tc = 0.0;
+        if ((r = cycle_ms(P0, tc)) != HJ_OK) return r;
+        const bool exact = P0.overlap_x >= 2 * P0.s - 2;
+        if (n_classical > 0 && tc * (double)((n_classical + P0.s - 1) / P0.s) >= best_t) continue;
+        hj_params P = P0;
+        if (std::isfinite(best_t))
+            P.max_cycles = std::max<int64_t>(1, std::min<int64_t>(P.max_cycles, (int64_t)(best_t / tc) + 2));
+        HJ_HIP(restore());
+        hj_info info{};
+        HJ_HIP(hipEventRecord(S.tev[0], st));
+        const hj_status sr = solve_2d_on(nx, ny, ld, hx, hy, dtype, f, xw, P, st, xs, ctl_of(S), &info);
+        HJ_HIP(hipEventRecord(S.tev[1], st));
+        HJ_HIP(hipEventSynchronize(S.tev[1]));
+        if (sr == HJ_ERR_HIP || sr == HJ_ERR_INVALID_ARG) return sr;
+        if (sr != HJ_OK) continue;
+        float e = 0.0f;
+        HJ_HIP(hipEventElapsedTime(&e, S.tev[0], S.tev[1]));
+        if (exact && info.cycles > 0) {
+            // an exact-regime cycle is s classical sweeps: more than
+            // (cycles - 1) s sweeps were needed
+            n_classical = std::max<int64_t>(n_classical, (info.cycles - 1) * P.s + 1);
+        }
+        if ((double)e < best_t) {
+            best_t = (double)e;
+            winner = P0;
+        }
+    }
+    g_err.clear();
+    if (!std::isfinite(best_t)) return fail(HJ_ERR_NOT_CONVERGED, "autotune_solve: no candidate reached trial_tol");
+    *best = winner;
+    best->max_cycles = tp->max_trial_cycles;
+    if (best_ms) *best_ms = best_t;
+    return HJ_OK;
+}
+
 hj_status hj_autotune_batch(const hj_problem *probs, int64_t nprob, hj_dtype dtype, void *stream,
                             hj_params *p2, hj_params *p1)
 {

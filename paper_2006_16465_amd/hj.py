@@ -72,6 +72,12 @@ class AdjointDesc(ctypes.Structure):
                 ("params", Params)]
 
 
+class TuneParams(ctypes.Structure):
+    _fields_ = [("trial_tol", ctypes.c_double), ("max_trial_cycles", ctypes.c_int64),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
 class Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("flags", ctypes.c_int32), ("nx", ctypes.c_int64),
                 ("ny", ctypes.c_int64), ("ld", ctypes.c_int64), ("hx", ctypes.c_double),
@@ -117,7 +123,7 @@ class HJError(RuntimeError):
 _lib = None
 EXPORTS = ("hj_params_default", "hj_solve_1d", "hj_solve_2d", "hj_solve_2d_noalloc", "hj_solve_2d_refined",
            "hj_residual",
-           "hj_solve_batched", "hj_autotune", "hj_autotune_batch", "hj_solve_vc_2d", "hj_vc_grad_a", "hj_solve_adjoint",
+           "hj_solve_batched", "hj_autotune", "hj_autotune_batch", "hj_autotune_solve", "hj_solve_vc_2d", "hj_vc_grad_a", "hj_solve_adjoint",
            "hj_axis_tiles",
            "hj_status_string", "hj_last_error", "hj_version")
 
@@ -151,6 +157,9 @@ def load():
     lib.hj_autotune.restype = i32
     lib.hj_autotune_batch.argtypes = [ctypes.POINTER(Problem), i64, i32, vp, P, P]
     lib.hj_autotune_batch.restype = i32
+    lib.hj_autotune_solve.argtypes = [i64, i64, i64, f64, f64, i32, vp, vp, ctypes.POINTER(TuneParams), vp, P,
+                                      ctypes.POINTER(f64)]
+    lib.hj_autotune_solve.restype = i32
     lib.hj_solve_vc_2d.argtypes = [ctypes.POINTER(VCProblem), vp, vp, P, vp, I]
     lib.hj_solve_vc_2d.restype = i32
     lib.hj_vc_grad_a.argtypes = [ctypes.POINTER(VCProblem), vp, vp, vp, i64, vp]
@@ -429,6 +438,34 @@ def solve_batched(problems, *, rel_tol=1e-8, tile=(64, 64), s=10, overlap=(18, 1
             ps = HJ_OK
         out.append(Info(ps, i.cycles, i.sweeps, i.rel_residual, i.r0_norm))
     return out
+
+
+def autotune_solve(f, x0=None, h=None, *, hx=None, hy=None, trial_tol=1e-6, max_trial_cycles=1_000_000,
+                   tile=None):
+    """Cycle shape that solves this 2D problem (f, from x0, default 0) to
+    trial_tol fastest, inexact overlaps included (hj_autotune_solve).
+    tile=(tx, ty) restricts the candidates to that tile.  Returns
+    (tile, s, overlap, ms of the winning trial)."""
+    import torch
+    hx = hx if hx is not None else h
+    hy = hy if hy is not None else hx
+    x0 = torch.zeros_like(f) if x0 is None else x0
+    _check_pair(f, x0)
+    ld = _ld(f)
+    if _ld(x0) != ld:
+        raise ValueError("f and x0 must share the row stride")
+    ny, nx = f.shape
+    tp = TuneParams()
+    tp.trial_tol, tp.max_trial_cycles, tp.flags = trial_tol, max_trial_cycles, 0
+    tp.tile_x, tp.tile_y = tile if tile is not None else (0, 0)
+    p = Params()
+    ms = ctypes.c_double()
+    with _device(f):
+        st = load().hj_autotune_solve(nx, ny, ld, float(hx), float(hy), _dtype_code(f), f.data_ptr(),
+                                      x0.data_ptr(), ctypes.byref(tp), _stream(f), ctypes.byref(p), ctypes.byref(ms))
+    if st != HJ_OK:
+        raise HJError(st, last_error())
+    return (p.tile_x, p.tile_y), p.s, (p.overlap_x, p.overlap_y), ms.value
 
 
 def autotune(dim, nx, ny=1, dtype=None):

@@ -266,3 +266,33 @@ def test_status_strings_and_defaults():
 def test_partition_count_agrees_with_oracle(orc, n, t, o):
     assert hj.axis_tiles(n, t, o) == len(orc.axis_tiles(n, t, o))
     assert hj.axis_tiles(0, 32, 0) == -1 and hj.axis_tiles(10, 8, 8) == -1
+
+
+def test_autotune_solve_rejects_invalid_arguments():
+    lib = hj.load()
+
+    def tp(**kw):
+        t = hj.TuneParams()
+        t.trial_tol, t.max_trial_cycles, t.tile_x, t.tile_y, t.flags = 1e-4, 1000, 0, 0, 0
+        for k, v in kw.items():
+            setattr(t, k, v)
+        return t
+
+    best = hj.Params()
+    ms = ctypes.c_double()
+
+    def call(t, nx=64, ny=64, ld=64, x0=FAKE):
+        return lib.hj_autotune_solve(nx, ny, ld, 0.01, 0.01, 0, FAKE, x0, ctypes.byref(t) if t else None, None,
+                                     ctypes.byref(best), ctypes.byref(ms))
+
+    assert call(None) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(trial_tol=0.0)) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(trial_tol=float("nan"))) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(max_trial_cycles=0)) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(flags=1)) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(tile_x=64)) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(tile_x=48, tile_y=32)) == hj.HJ_ERR_UNSUPPORTED
+    assert call(tp(), ld=32) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(), x0=None) == hj.HJ_ERR_INVALID_ARG
+    assert hj.last_error()
+
