@@ -94,6 +94,29 @@ __device__ __forceinline__ float dpp_shift(float v)
         float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
 
+// Shifted like dpp_shift, but lanes whose source lies outside the 16-lane
+// row keep `old` (bound_ctrl off): a register that holds the frozen x-halo
+// in the first (row_shr) or last (row_shl) lane of each row keeps it there
+// while every other lane receives its neighbour's value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_keep(double old, double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned long long o = __builtin_bit_cast(unsigned long long, old);
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    const int hi =
+        __builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_keep(float old, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                  __builtin_bit_cast(int, v), CTRL, 0xf, 0xf,
+                                                                  false));
+}
+
 // s * 1/4 + b with one rounding, in the three-address VOP3 form (the compiler's
 // two-address v_fmac would first copy b, which stays live across sweeps)
 // (0.25 is not an inline constant and VOP3 takes no literal: it rides in SGPRs)
@@ -323,25 +346,21 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
         for (int c = 0; c < C; ++c) prev[c] = up[c];
 #pragma unroll
         for (int i = 0; i < R; ++i) {
-            const T wl = dpp_shift<kDppRowShr1>(x[i][C - 1]);
-            const T er = dpp_shift<kDppRowShl1>(x[i][0]);
+            // x-neighbours from the lanes beside; the first / last lane of
+            // each DPP row keeps the frozen halo (or the boundary 0) in hw / he
+            hw[i] = dpp_keep<kDppRowShr1>(hw[i], x[i][C - 1]);
+            he[i] = dpp_keep<kDppRowShl1>(he[i], x[i][0]);
             T nw[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const T w = c > 0 ? x[i][c - 1] : wl;
-                const T e = c < C - 1 ? x[i][c + 1] : er;
-                T we = w + e;
-                // the halo registers are 0 except in the first / last lane of a
-                // DPP row, where the shifted value is 0: the sum stays W + E
-                if (c == 0) we = we + hw[i];
-                if (c == C - 1) we = we + he[i];
+                const T w = c > 0 ? x[i][c - 1] : hw[i];
+                const T e = c < C - 1 ? x[i][c + 1] : he[i];
+                const T we = w + e;
                 const T below = i < R - 1 ? x[i + 1][c] : dn[c];
                 const T sn = prev[c] + below;
                 if (FIRST) {
                     if (RES && i >= rlo && i < rhi && c >= clo && c < chi) {
-                        const double wa = c > 0 ? (double)w : (double)wl + (double)hw[i];
-                        const double ea = c < C - 1 ? (double)e : (double)er + (double)he[i];
-                        const double rr = res2((double)bq[i][c], (double)x[i][c], wa, ea,
+                        const double rr = res2((double)bq[i][c], (double)x[i][c], (double)w, (double)e,
                                                (double)prev[c], (double)below, g.wx, g.wy);
                         rsq += rr * rr;
                     }
