@@ -32,14 +32,20 @@
  * ceil((b - a) / 2) points.  The 2D partition is the product of the per-axis
  * partitions.
  *
- * Arithmetic (IEEE round-to-nearest, no fused multiply-add, no flush to zero):
+ * Arithmetic (IEEE round-to-nearest, no flush to zero; the compiler does not
+ * contract to fused multiply-add):
  *   1D:          x_i <- (h^2 f_i + (x_{i-1} + x_{i+1})) * 0.5
  *   2D, hx==hy:  x   <- (h^2 f + ((x_W + x_E) + (x_S + x_N))) * 0.25
  *   2D, hx!=hy:  x   <- (f + (wx (x_W + x_E) + wy (x_S + x_N))) * dinv
  * with h^2 f rounded once, wx = 1/hx^2, wy = 1/hy^2, dinv = 1/(2 wx + 2 wy),
- * W/E the x neighbours (same row), S/N the y neighbours (adjacent rows).  In
- * FP64 the iterates are therefore bit-reproducible and independent of the
- * order in which tiles run.
+ * W/E the x neighbours (same row), S/N the y neighbours (adjacent rows).  The
+ * register-resident kernels evaluate the first two as one fused multiply-add
+ * of the neighbour sum with the exact factor 0.5 / 0.25 and the prescaled
+ * h^2 f * 0.5 / * 0.25; scaling by a power of two commutes with rounding, so
+ * this is the two-step result bit for bit whenever the values involved are
+ * normal numbers (magnitudes above 2^-1020 in FP64, 2^-124 in FP32; subnormal
+ * intermediates can differ in the last place).  In FP64 the iterates are
+ * therefore bit-reproducible and independent of the order in which tiles run.
  *
  * Residual: r = f - A x over the interior, its 2-norm accumulated in FP64 with
  * a fixed-order reduction (deterministic run to run).  A solve stops at the
