@@ -56,6 +56,19 @@ def cycle_bytes_per_launch(n, tile, overlap, esize=8):
     return esize * (ntx * nty * per_tile + n * n)
 
 
+def vc_cycle_bytes(nx, ny, tile, overlap):
+    """Algorithmic HBM bytes of one variable-coefficient cycle (FP64): every
+    tile reads x over its interior and edge halo, a at the same nodes (the
+    face weights of its points), f over its interior, and writes its owned
+    points."""
+    from paper_2006_16465_amd import hj
+    tx, ty = tile
+    nt = hj.axis_tiles(nx, tx, overlap[0]) * hj.axis_tiles(ny, ty, overlap[1])
+    ex, ey = min(tx, nx), min(ty, ny)
+    halo = (ex + 2) * (ey + 2) - 4
+    return 8 * (nt * (2 * halo + ex * ey) + nx * ny)
+
+
 def sweep_bytes_per_launch(n, esize=8):
     """Algorithmic HBM bytes of one global sweep: read x and f, write x."""
     return 3 * esize * n * n
@@ -798,17 +811,27 @@ def diffusion_rows(torch, hj, stream):
     a = torch.from_numpy(W.diffusion_coefficient(n, 0.05, 1.0, 7)).cuda()
     f = torch.from_numpy(W.rhs_2d_modes(n, n, 8, 0.0, 0)).cuda()[None]
     u = torch.zeros_like(f)
-    hj.solve_vc_2d(a, f, u, h, rel_tol=0.0, max_cycles=4, **shape)
     K = 40
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    u.zero_()
-    e0.record(stream)
-    hj.solve_vc_2d(a, f, u, h, rel_tol=0.0, max_cycles=K, **shape)
-    e1.record(stream)
-    e1.synchronize()
-    us = e0.elapsed_time(e1) * 1e3 / K
+
+    def vc_cycle_us(lds):
+        hj.solve_vc_2d(a, f, u, h, rel_tol=0.0, max_cycles=4, lds_kernel=lds, **shape)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        u.zero_()
+        e0.record(stream)
+        hj.solve_vc_2d(a, f, u, h, rel_tol=0.0, max_cycles=K, lds_kernel=lds, **shape)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / K
+
+    us, us_lds = vc_cycle_us(False), vc_cycle_us(True)
+    vbytes = vc_cycle_bytes(n, n, shape["tile"], shape["overlap"])
     out["vc_cycle_1024"] = {"tile": list(shape["tile"]), "s": shape["s"], "overlap": list(shape["overlap"]),
-                            "us_per_cycle": round(us, 1), "gsweeps_per_s": round(n * n * shape["s"] / us / 1e3, 1)}
+                            "us_per_cycle": round(us, 1), "gsweeps_per_s": round(n * n * shape["s"] / us / 1e3, 1),
+                            "body": "register-resident tiles",
+                            "us_per_cycle_lds_body": round(us_lds, 1),
+                            "algorithmic_bytes_per_cycle": vbytes,
+                            "achieved_gbs": round(vbytes / us / 1e3, 1),
+                            "frac_of_hbm_peak": round(vbytes / us / 1e3 / HBM_PEAK_GBS, 3)}
 
     # the configuration's own size, 16 right-hand sides: measured cycle rate
     # of the batched forward and adjoint solves and a projection of the time
@@ -843,6 +866,7 @@ def diffusion_rows(torch, hj, stream):
         log(f"differentiable: {what}: rel residuals at {c1}: {r1}; at {c2}: {r2}")
         return {"batch": B, "cycles_measured": [c1, c2], "ms_per_cycle_batch": round(per_cycle_ms, 3),
                 "gsweeps_per_s": round(B * n * n * shape["s"] / per_cycle_ms / 1e6, 1),
+                "achieved_gbs": round(B * vbytes / per_cycle_ms / 1e6, 1),
                 "rel_residual_at_c1_max": max(r1), "rel_residual_at_c2_max": max(r2),
                 "per_cycle_factor_worst": max((b2 / b1) ** (1.0 / (c2 - c1)) for b1, b2 in zip(r1, r2)),
                 "projected_cycles_to_1e-10": round(worst) if finite else None,

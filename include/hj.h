@@ -104,8 +104,9 @@ typedef enum hj_dtype {
 
 typedef enum hj_method { HJ_HIERARCHICAL = 0, HJ_GLOBAL = 1 } hj_method;
 
-/* hj_params.flags: run every 2D cycle on the LDS ping-pong kernel instead of
- * the register-resident one (same iterates; for comparison and testing). */
+/* hj_params.flags: run every 2D cycle (constant- and variable-coefficient)
+ * on the LDS ping-pong kernel instead of the register-resident one (same
+ * iterates; for comparison and testing). */
 #define HJ_FLAG_LDS_KERNEL 0x1
 /* hj_params.flags, 1D solves: one kernel launch per cycle (HJ_GLOBAL: per
  * sweep) even where one workgroup can run the whole solve (same iterates; for
@@ -375,7 +376,10 @@ hj_status hj_autotune_batch(const hj_problem *probs, int64_t nprob, hj_dtype dty
  *   (A u)_p = sum over the 4 faces of p: a_face (u_p - u_neighbour) / h^2,
  * u = 0 on the boundary.  Jacobi update u_p <- (f_p + sum a_face u_nb / h^2) /
  * sum a_face / h^2; the hierarchical cycle, overlap and stopping rule are
- * those of hj_solve_2d (no register-resident kernel: LDS ping-pong). */
+ * those of hj_solve_2d.  Tiles (tile_x, tile_y) from {16, 32, 64}^2; grids
+ * holding a full tile in each direction run register-resident tiles (two
+ * rows of tile_x / 16 points a lane), smaller ones, or any with
+ * HJ_FLAG_LDS_KERNEL, the LDS ping-pong tile: same iterates either way. */
 typedef struct hj_vc_problem {
     int64_t nx, ny;        /* interior grid */
     int64_t ld;            /* leading dimension of f, u, lam (elements, >= nx) */

@@ -392,6 +392,7 @@ hj::GeomVC make_geom_vc(const hj_vc_problem &pr, const hj_params &p)
     g.lda = pr.lda;
     g.ihx2 = 1.0 / (pr.hx * pr.hx);
     g.ihy2 = 1.0 / (pr.hy * pr.hy);
+    g.reg = (p.flags & HJ_FLAG_LDS_KERNEL) ? 0 : 1;
     return g;
 }
 

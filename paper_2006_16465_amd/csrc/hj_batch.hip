@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kNT) void k_batch_cycle1d(const BProb *__restrict__
     post_partial_at<kNT>(rsq, &part[P.part0 + blk]);
 }
 
-// Variable-coefficient 2D problems (dim 3, FP64, plain): the LDS tile body of
+// Variable-coefficient 2D problems (dim 3, FP64, plain): the tile bodies of
 // the single-problem kernel (hj_vc_tile.h).
 template <int TX, int TY>
 __global__ __launch_bounds__((vc_threads<TX, TY>())) void k_batch_cycle_vc(const BProb *__restrict__ probs,
@@ -194,7 +194,7 @@ __global__ __launch_bounds__((vc_threads<TX, TY>())) void k_batch_cycle_vc(const
     double *xout;
     main_arrays<double>(P, S, xin, xout);
     const int tile = (int)(w - P.item0);
-    const double rsq = lds_tile_vc<TX, TY, true>(P.gv, tile, (const double *)P.f, xin, xout, s);
+    const double rsq = tile_vc<TX, TY, true>(P.gv, tile, (const double *)P.f, xin, xout, s);
     post_partial_at<vc_threads<TX, TY>()>(rsq, &part[P.part0 + tile]);
 }
 

@@ -99,6 +99,7 @@ struct GeomVC {
     const double *a;  // (ny+2) x lda node coefficients
     int64_t lda;
     double ihx2, ihy2;
+    int reg;          // 1: register-resident tiles where the grid holds a full tile
 };
 int64_t cycle_vc_blocks(const GeomVC &g);
 int64_t sweep_vc_blocks(const GeomVC &g);

@@ -23,7 +23,7 @@ __global__ __launch_bounds__((vc_threads<TX, TY>())) void k_cycle2d_vc(GeomVC g,
         if (blockIdx.x == 0 && red.nb_prev > 0)
             judge_partials<NT>(red.part_prev, red.nb_prev, red.ctrl, red.c - 1, tol);
     }
-    const double rsq = lds_tile_vc<TX, TY, RES>(g, xcd_tile(blockIdx.x, gridDim.x), f, xin, xout, nsub);
+    const double rsq = tile_vc<TX, TY, RES>(g, xcd_tile(blockIdx.x, gridDim.x), f, xin, xout, nsub);
     if (RES) post_partial<NT>(rsq, red.part_cur);
 }
 

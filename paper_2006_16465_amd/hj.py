@@ -508,16 +508,16 @@ def _vc_problem(a, f, hx, hy):
 
 def solve_vc_2d(a, f, u, h=None, *, hx=None, hy=None, tile=(32, 32), s=8, overlap=(0, 0),
                 method="hierarchical", rel_tol=1e-10, max_cycles=1_000_000, check_every=0,
-                allow_not_converged=False):
+                allow_not_converged=False, lds_kernel=False):
     """Solve -div(a grad u_b) = f_b for a batch (hj_solve_vc_2d); u (same shape as f) in/out.
-    Returns one Info per right-hand side."""
+    Returns one Info per right-hand side.  lds_kernel: HJ_FLAG_LDS_KERNEL."""
     _check_pair(f, u)
     hx = hx if hx is not None else h
     hy = hy if hy is not None else hx
     pr = _vc_problem(a, f, hx, hy)
     if not u.is_contiguous():
         raise ValueError("u must be contiguous")
-    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap)
+    p = make_params(tile, s, method, rel_tol, max_cycles, check_every, overlap, lds_kernel=lds_kernel)
     infos = (_Info * pr.batch)()
     with _device(f):
         st = load().hj_solve_vc_2d(ctypes.byref(pr), f.data_ptr(), u.data_ptr(), ctypes.byref(p),

@@ -38,16 +38,54 @@ def prob():
     return nx, ny, hx, hy, a, f
 
 
-@pytest.mark.parametrize("tile,s,ov", [((32, 32), 8, (0, 0)), ((16, 16), 4, (6, 6)), ((64, 16), 3, (2, 2))])
-def test_vc_fixed_cycles_match_oracle(orc, prob, tile, s, ov):
+# 64 x 48 grid: the first four shapes hold a full tile in each direction and
+# run register-resident tiles by default; (16, 64) and (32, 64) are taller
+# than the grid and run the LDS tile.  lds_kernel forces the LDS tile.
+@pytest.mark.parametrize("lds", [False, True], ids=["default", "lds"])
+@pytest.mark.parametrize("tile,s,ov", [((32, 32), 8, (0, 0)), ((16, 16), 4, (6, 6)), ((64, 16), 3, (2, 2)),
+                                       ((64, 32), 8, (14, 14)), ((16, 64), 5, (8, 8)), ((32, 64), 2, (0, 0))])
+def test_vc_fixed_cycles_match_oracle(orc, prob, tile, s, ov, lds):
     nx, ny, hx, hy, a, f = prob
     U = torch.zeros_like(dev(f))
-    hj.solve_vc_2d(dev(a), dev(f), U, hx=hx, hy=hy, tile=tile, s=s, overlap=ov, rel_tol=0.0, max_cycles=5)
+    hj.solve_vc_2d(dev(a), dev(f), U, hx=hx, hy=hy, tile=tile, s=s, overlap=ov, rel_tol=0.0, max_cycles=5,
+                   lds_kernel=lds)
     got = host(U)
     for b in range(f.shape[0]):
         want = orc.vc_solve_2d(a, f[b], np.zeros((ny, nx)), hx, hy, tile=tile, s=s, overlap=ov,
                                tol=0.0, max_cycles=5)[0]
         assert np.array_equal(got[b], want), f"batch {b}"
+
+
+@pytest.mark.parametrize("tile,s,ov", [((64, 32), 8, (14, 14)), ((32, 64), 6, (10, 10)), ((16, 32), 3, (0, 0)),
+                                       ((64, 64), 4, (6, 6))])
+def test_vc_register_tiles_on_a_ragged_grid_match_oracle(orc, tile, s, ov):
+    """150 x 75 with anisotropic spacing: several tiles per axis with the
+    last one moved left to end at the grid edge, so the ownership split
+    between overlapping tiles is uneven; register-resident tiles (default)
+    and the LDS tile must both give the oracle's iterates bit for bit, after
+    fixed cycles and at the tolerance (the residual fused into the load)."""
+    nx, ny = 150, 75
+    hx, hy = 1.0 / (nx + 1), 1.3 / (ny + 1)
+    a = np.exp(W.grf_2d(ny + 2, nx + 2, 0.1, 1.0, hx, seed=3))
+    f = np.stack([W.rhs_2d_modes(nx, ny, 8, 0.1, 40 + b) for b in range(2)])
+    x0 = np.stack([W.rhs_random((ny, nx), 50 + b) for b in range(2)])
+    kw = dict(tile=tile, s=s, overlap=ov)
+    for lds in (False, True):
+        U = dev(x0)
+        hj.solve_vc_2d(dev(a), dev(f), U, hx=hx, hy=hy, rel_tol=0.0, max_cycles=3, lds_kernel=lds, **kw)
+        got = host(U)
+        for b in range(2):
+            want = orc.vc_solve_2d(a, f[b], x0[b], hx, hy, tol=0.0, max_cycles=3, **kw)[0]
+            assert np.array_equal(got[b], want), f"lds={lds} b={b} fixed cycles"
+    U = dev(x0)
+    infos = hj.solve_vc_2d(dev(a), dev(f), U, hx=hx, hy=hy, rel_tol=1e-7, **kw)
+    got = host(U)
+    for b in range(2):
+        xo, co, relo, _ = orc.vc_solve_2d(a, f[b], x0[b], hx, hy, tol=1e-7, **kw)
+        say(f"vc ragged {tile} s={s} b={b}: gpu cycles {infos[b].cycles}, oracle {co}")
+        assert infos[b].cycles == co
+        assert np.array_equal(got[b], xo)
+        assert abs(infos[b].rel_residual - relo) <= 1e-9 * relo
 
 
 def test_vc_classical_and_tolerance_match_oracle(orc, prob):
