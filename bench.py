@@ -6,15 +6,21 @@ One step = solving the five seeded right-hand sides (8 random separable sine
 modes each, seeds 0-4) from x0 = 0, one after another, with inputs already
 resident in HBM.  `value` is the mean time to tolerance per problem.
 
-Default parameters: 64 x 128 tiles, s = 12 sub-iterations, overlap 22 points
-in x and y (overlap = 2s - 2: the owned points of every tile lie beyond the
-reach of the frozen halo within s sweeps, so a cycle advances s classical
-sweeps with one pass over HBM).  The paper's own setting (32 x 32, s = 16, no
-overlap) and the global-memory baseline are timed beside it, as are the
-512 x 512 experiment of Sec. 4.2 (32 x 32 tiles, s in {1, 4, 8, 16, 32}), the
-mixed-precision, batched, variable-coefficient, 1D and paper-replica rows.
+Default parameters: 64 x 128 tiles, s = 16 sub-iterations, overlap 22 points
+in x and y: the shape hj_autotune_solve picks on seed 5, a right-hand side of
+the same recipe that is not timed.  With overlap 2s - 2 (the exact regime) no
+owned point is reached by the frozen halo within s sweeps and a cycle is
+exactly s classical sweeps; at s = 16, o = 22 the nearest owned points sit
+four points inside its reach, where the halo's weight after s sweeps is
+4.7e-6 (halo_leak below), and every seed needs the exact regime's cycle
+count ceil(classical sweeps / s).  The exact-regime shape of the earlier
+default (s = 12, o = 22) is timed beside it (`exact_regime`; the
+mixed-precision rows use it too), as are the paper's own setting (32 x 32,
+s = 16, no overlap), the global-memory baseline, the 512 x 512 experiment of
+Sec. 4.2 (32 x 32 tiles, s in {1, 4, 8, 16, 32}), the batched,
+variable-coefficient, 1D and paper-replica rows.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--s 12] [--tile 64 128]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--s 16] [--tile 64 128]
                     [--overlap 22 22] [--seeds 0 1 2 3 4] [--no-cpu] [--no-global]
                     [--no-paper-config] [--no-c2] ...
 
@@ -135,7 +141,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--tile", type=int, nargs=2, default=[64, 128])
-    ap.add_argument("--s", type=int, default=12)
+    ap.add_argument("--s", type=int, default=16)
     ap.add_argument("--overlap", type=int, nargs=2, default=[22, 22])
     ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1, 2, 3, 4])
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -157,6 +163,10 @@ def main():
     ap.add_argument("--no-diffusion", action="store_true",
                     help="skip the variable-coefficient / adjoint rows")
     ap.add_argument("--no-1d", action="store_true", help="skip the 1D rows")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the exact-regime row (s = --exact-s, overlap 2s - 2)")
+    ap.add_argument("--exact-s", type=int, default=12,
+                    help="s of the exact-regime row and of the mixed-precision rows")
     ap.add_argument("--no-tuned", action="store_true",
                     help="skip the row with the shape hj_autotune_solve picks on an independent seed")
     ap.add_argument("--no-c2", action="store_true",
@@ -308,6 +318,24 @@ def main():
             "timing": f"{args.warmup} warmup + {args.steps} timed steps, per-seed medians",
         }
 
+    s_x = args.exact_s
+    ov_exact = (2 * s_x - 2, 2 * s_x - 2)
+    if not args.no_exact and (s_x, ov_exact) != (s, tuple(ov)):
+        log(f"exact regime: s = {s_x}, overlap {ov_exact}")
+        wall_x, per_x = timed("hierarchical", args.steps, args.warmup, s=s_x, ov=ov_exact)
+        ev_ms_x = np.array([[ms for ms, _ in step] for step in per_x])
+        t_x = full_launch_seconds(torch, hj, fs[-1], xs[-1], h, tile, s_x, ov_exact, stream)
+        b_x = cycle_bytes_per_launch(n, tile, ov_exact)
+        extra["exact_regime"] = {
+            "tile": list(tile), "s": s_x, "overlap": list(ov_exact), "halo_leak": 0.0,
+            "avg_launch_us": round(t_x * 1e6, 2),
+            "roofline_frac": round(b_x / t_x / 1e9 / HBM_PEAK_GBS, 4),
+            "ms_per_problem": round(wall_x / args.steps / nprob, 3),
+            "cycles_per_seed": dict(zip(map(str, args.seeds), [i.cycles for _, i in per_x[0]])),
+            "ms_per_seed": dict(zip(map(str, args.seeds), [round(float(v), 3) for v in np.median(ev_ms_x, axis=0)])),
+            "headline_speedup_over_it": round(wall_x / wall_h, 3),
+        }
+
     if not args.no_tuned:
         # the right-hand-side tuner run on an independent right-hand side of
         # the same workload (seed 5, not timed here), its shape then solving
@@ -318,19 +346,20 @@ def main():
         tt, ts, tov, _ = hj.autotune_solve(f5, None, h, trial_tol=args.tol)
         tune_s = time.perf_counter() - t0
         del f5
-        wall_t, per_t = timed("hierarchical", 1, 1, tile=tt, s=ts, ov=tov)
+        wall_t, per_t = timed("hierarchical", args.steps, args.warmup, tile=tt, s=ts, ov=tov)
         extra["tuned_shape"] = {
             "tile": list(tt), "s": ts, "overlap": list(tov), "tuning_s": round(tune_s, 2),
             "tuned_on": "seed 5 (hj_autotune_solve, trial solves to the same tolerance, inexact overlaps included)",
-            "ms_per_problem": round(wall_t / nprob, 3),
+            "ms_per_problem": round(wall_t / args.steps / nprob, 3),
             "cycles_per_seed": dict(zip(map(str, args.seeds), [i.cycles for _, i in per_t[0]])),
-            "ms_per_seed": dict(zip(map(str, args.seeds), [round(ms, 3) for ms, _ in per_t[0]])),
+            "ms_per_seed": dict(zip(map(str, args.seeds), [round(float(v), 3) for v in np.median(
+                np.array([[ms for ms, _ in step] for step in per_t]), axis=0)])),
         }
         log(f"tuned shape: {extra['tuned_shape']}")
     if not args.no_c2:
         extra["poisson2d_512"] = c2_rows(torch, hj, stream)
     if not args.no_mixed:
-        extra["mixed_precision"] = mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream)
+        extra["mixed_precision"] = mixed_rows(args, torch, hj, fs, xs, h, tile, s_x, ov_exact, stream)
     if not args.no_batch:
         del fs, xs
         torch.cuda.empty_cache()
@@ -363,7 +392,8 @@ def main():
             "workload": f"poisson2d_{n}: 2D 5-point Poisson {n}x{n}, Dirichlet 0, f = 8 random separable "
                         f"sine modes (seeds {args.seeds}), x0 = 0, to rel. residual {args.tol:g}; one step "
                         f"= all seeds solved once; value = mean ms per problem",
-            "n": n, "tile": list(tile), "s": s, "overlap": list(ov), "tol": args.tol,
+            "n": n, "tile": list(tile), "s": s, "overlap": list(ov), "halo_leak": halo_leak(s, min(ov)),
+            "tol": args.tol,
             "seeds": args.seeds, "method": "hierarchical", "check_every": args.check_every,
         },
         "roofline": roofline,
@@ -371,6 +401,24 @@ def main():
         **extra,
     }
     print(json.dumps(line), flush=True)
+
+
+def halo_leak(s, o):
+    """Weight of the frozen halo in an owned point after the s sweeps of a
+    cycle, at the owned point nearest the tile edge (ceil(o/2) + 1 points
+    from the halo column).  A 2D Jacobi sweep averages the four neighbours, so
+    an iterate is a random-walk expectation and the stale halo enters with
+    the probability that the walk's x-coordinate (a lazy walk: -1, 0, +1 with
+    probabilities 1/4, 1/2, 1/4) reaches the halo within s - 1 steps (the
+    first sweep reads the halo at its current value).  By the reflection
+    principle that is P(X <= -d) + P(X <= -d - 1), X = B(2(s-1), 1/2) - (s-1).
+    0 in the exact regime (o >= 2s - 2)."""
+    from math import comb
+    d, m = -(-o // 2) + 1, s - 1
+    if d > m:
+        return 0.0
+    tail = lambda k: sum(comb(2 * m, j) for j in range(0, m - k + 1)) / 4.0 ** m  # P(X <= -k)
+    return float(tail(d) + tail(d + 1))
 
 
 def full_launch_seconds(torch, hj, f, x, h, tile, s, ov, stream, k1=8, k2=32):

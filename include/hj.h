@@ -338,7 +338,13 @@ hj_status hj_autotune(int32_t dim, int64_t nx, int64_t ny, hj_dtype dtype, void 
  * the one that got there first, by wall time on the stream:
  *   tiles 32x32, 64x32, 32x64, 64x64, 64x128 that fit the grid (or only
  *   (tile_x, tile_y) when given), s in {4, 8, 12, 16, 24, 32}, even overlaps
- *   {0, 2, 4, 8, 2s - 2} below the tile; exact-regime shapes first.
+ *   below the tile: 2s - 2 (exact regime, tried first), then the near-exact
+ *   2s - 6, 2s - 10, 3s/2 (rounded up to even), s + 6, s + 2, then 8, 4, 2,
+ *   0.  Near-exact overlaps keep every owned point a few points inside the
+ *   stale halo's reach, so the halo's influence on it after s sweeps is
+ *   small; on many right-hand sides they need the exact regime's cycle
+ *   count with less redundant loading, on some they stall: the trial on the
+ *   caller's problem decides.
  * A candidate is skipped without a trial when its measured time per cycle
  * times ceil(N / s) already exceeds the best time, N being the classical
  * sweep count the exact-regime trials revealed (a cycle gains at most s

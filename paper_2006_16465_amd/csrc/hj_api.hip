@@ -1426,7 +1426,11 @@ hj_status hj_autotune_solve(int64_t nx, int64_t ny, int64_t ld, double hx, doubl
     hj_status r;
     if ((r = check_solve_2d(nx, ny, ld, hx, hy, dtype, f, x0, &base)) != HJ_OK) return r;
 
-    // candidates: exact regime first (they reveal the classical sweep count)
+    // candidates: exact regime first (they reveal the classical sweep count),
+    // then overlaps a little short of it (owned points a few points inside
+    // the stale halo's reach, where its influence is small and the count
+    // often stays that of the exact regime at less redundant loading), then
+    // small overlaps
     std::vector<hj_params> cands;
     const int tiles[][2] = {{64, 128}, {64, 64}, {32, 64}, {64, 32}, {32, 32}};
     for (const bool exact : {true, false}) {
@@ -1434,7 +1438,8 @@ hj_status hj_autotune_solve(int64_t nx, int64_t ny, int64_t ld, double hx, doubl
             const int tx = tp->tile_x ? tp->tile_x : t[0], ty = tp->tile_y ? tp->tile_y : t[1];
             if (tp->tile_x && (t[0] != tiles[0][0] || t[1] != tiles[0][1])) continue;  // the given tile once
             for (const int s : {32, 24, 16, 12, 8, 4}) {
-                for (const int o : {2 * s - 2, 8, 4, 2, 0}) {
+                const int three_halves = (3 * s / 2 + 1) & ~1;
+                for (const int o : {2 * s - 2, 2 * s - 6, 2 * s - 10, three_halves, s + 6, s + 2, 8, 4, 2, 0}) {
                     if ((o == 2 * s - 2) != exact || o >= std::min(tx, ty) || o < 0) continue;
                     if (!exact && o >= 2 * s - 2) continue;
                     hj_params P = base;
