@@ -345,20 +345,27 @@ hj_status hj_autotune(int32_t dim, int64_t nx, int64_t ny, hj_dtype dtype, void 
  *   small; on many right-hand sides they need the exact regime's cycle
  *   count with less redundant loading, on some they stall: the trial on the
  *   caller's problem decides.
+ * With nrhs > 1 every candidate solves each right-hand side in turn (all
+ * from x0) and is scored by the sum of the times; a candidate that misses
+ * trial_tol on any of them is dropped, so a shape that only suits some of
+ * the caller's right-hand sides loses.
  * A candidate is skipped without a trial when its measured time per cycle
- * times ceil(N / s) already exceeds the best time, N being the classical
- * sweep count the exact-regime trials revealed (a cycle gains at most s
- * classical sweeps); each trial is capped at the cycles that could still
- * beat the best, and at max_trial_cycles.  best gets the winner
- * (hierarchical, rel_tol = trial_tol, other fields defaulted), *best_ms its
- * time (may be NULL).  HJ_ERR_NOT_CONVERGED if no candidate reached
- * trial_tol within max_trial_cycles. */
+ * times the sum over right-hand sides of ceil(N / s) already exceeds the
+ * best time, N being the classical sweep count the exact-regime trials
+ * revealed for that right-hand side (a cycle gains at most s classical
+ * sweeps); each trial is capped at the cycles that could still beat the
+ * best, and at max_trial_cycles.  best gets the winner (hierarchical,
+ * rel_tol = trial_tol, other fields defaulted), *best_ms its time (summed
+ * over right-hand sides; may be NULL).  HJ_ERR_NOT_CONVERGED if no
+ * candidate reached trial_tol within max_trial_cycles on every right-hand
+ * side. */
 typedef struct hj_tune_params {
     double trial_tol;         /* > 0: relative residual each trial solve must reach */
     int64_t max_trial_cycles; /* >= 1: cap per trial */
     int32_t tile_x, tile_y;   /* 0, 0: all candidate tiles; else only this tile (a 2D tile shape) */
     int32_t flags;            /* must be 0 */
-    int32_t pad;
+    int32_t nrhs;             /* 0 or 1: f is one right-hand side; 2..1024: f holds nrhs of them */
+    int64_t rhs_stride;       /* elements from one right-hand side to the next (>= ny * ld if nrhs > 1) */
 } hj_tune_params;
 
 hj_status hj_autotune_solve(int64_t nx, int64_t ny, int64_t ld, double hx, double hy, hj_dtype dtype,

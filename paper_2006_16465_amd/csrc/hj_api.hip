@@ -1416,6 +1416,8 @@ hj_status hj_autotune_solve(int64_t nx, int64_t ny, int64_t ld, double hx, doubl
         return fail(HJ_ERR_INVALID_ARG, "trial_tol must be finite and > 0");
     if (tp->max_trial_cycles < 1) return fail(HJ_ERR_INVALID_ARG, "max_trial_cycles must be >= 1");
     if (tp->flags != 0) return fail(HJ_ERR_INVALID_ARG, "tune flags must be 0");
+    if (tp->nrhs < 0 || tp->nrhs > 1024) return fail(HJ_ERR_INVALID_ARG, "nrhs must be in [0, 1024]");
+    const int nrhs = tp->nrhs > 1 ? tp->nrhs : 1;
     if ((tp->tile_x == 0) != (tp->tile_y == 0)) return fail(HJ_ERR_INVALID_ARG, "give both tile extents or neither");
     if (tp->tile_x && !hj::cycle2d_supported(tp->tile_x, tp->tile_y))
         return fail(HJ_ERR_UNSUPPORTED, "unsupported 2D tile shape");
@@ -1425,6 +1427,12 @@ hj_status hj_autotune_solve(int64_t nx, int64_t ny, int64_t ld, double hx, doubl
     base.max_cycles = tp->max_trial_cycles;
     hj_status r;
     if ((r = check_solve_2d(nx, ny, ld, hx, hy, dtype, f, x0, &base)) != HJ_OK) return r;
+    if (nrhs > 1 && (tp->rhs_stride < 0 || tp->rhs_stride / ld < ny))  // rhs_stride >= ny * ld, no overflow
+        return fail(HJ_ERR_INVALID_ARG, "rhs_stride must be >= ny * ld when nrhs > 1");
+    const size_t es0 = esize(dtype);
+    auto rhs = [&](int k) { return (const void *)((const char *)f + (size_t)k * (size_t)tp->rhs_stride * es0); };
+    for (int k = 1; k < nrhs; ++k)
+        if ((r = check_solve_2d(nx, ny, ld, hx, hy, dtype, rhs(k), x0, &base)) != HJ_OK) return r;
 
     // candidates: exact regime first (they reveal the classical sweep count),
     // then overlaps a little short of it (owned points a few points inside
@@ -1502,38 +1510,56 @@ hj_status hj_autotune_solve(int64_t nx, int64_t ny, int64_t ld, double hx, doubl
         return HJ_OK;
     };
     double best_t = INFINITY;
-    int64_t n_classical = 0;  // lower bound on the classical sweep count to trial_tol
+    // per right-hand side, a lower bound on its classical sweep count to trial_tol
+    std::vector<int64_t> n_classical((size_t)nrhs, 0);
     hj_params winner = cands[0];
     for (const hj_params &P0 : cands) {
         double tc = 0.0;
         if ((r = cycle_ms(P0, tc)) != HJ_OK) return r;
         const bool exact = P0.overlap_x >= 2 * P0.s - 2;
-        if (n_classical > 0 && tc * (double)((n_classical + P0.s - 1) / P0.s) >= best_t) continue;
-        hj_params P = P0;
-        if (std::isfinite(best_t))
-            P.max_cycles = std::max<int64_t>(1, std::min<int64_t>(P.max_cycles, (int64_t)(best_t / tc) + 2));
-        HJ_HIP(restore());
-        hj_info info{};
-        HJ_HIP(hipEventRecord(S.tev[0], st));
-        const hj_status sr = solve_2d_on(nx, ny, ld, hx, hy, dtype, f, xw, P, st, xs, ctl_of(S), &info);
-        HJ_HIP(hipEventRecord(S.tev[1], st));
-        HJ_HIP(hipEventSynchronize(S.tev[1]));
-        if (sr == HJ_ERR_HIP || sr == HJ_ERR_INVALID_ARG) return sr;
-        if (sr != HJ_OK) continue;
-        float e = 0.0f;
-        HJ_HIP(hipEventElapsedTime(&e, S.tev[0], S.tev[1]));
-        if (exact && info.cycles > 0) {
-            // an exact-regime cycle is s classical sweeps: more than
-            // (cycles - 1) s sweeps were needed
-            n_classical = std::max<int64_t>(n_classical, (info.cycles - 1) * P.s + 1);
+        bool known = true;
+        double floor_t = 0.0;
+        for (const int64_t nc : n_classical) {
+            known = known && nc > 0;
+            floor_t += tc * (double)((nc + P0.s - 1) / P0.s);
         }
-        if ((double)e < best_t) {
-            best_t = (double)e;
+        if (known && floor_t >= best_t) continue;
+        double total = 0.0;
+        bool ok = true;
+        for (int k = 0; k < nrhs && ok; ++k) {
+            hj_params P = P0;
+            if (std::isfinite(best_t))
+                P.max_cycles = std::max<int64_t>(
+                    1, std::min<int64_t>(P.max_cycles, (int64_t)((best_t - total) / tc) + 2));
+            HJ_HIP(restore());
+            hj_info info{};
+            HJ_HIP(hipEventRecord(S.tev[0], st));
+            const hj_status sr = solve_2d_on(nx, ny, ld, hx, hy, dtype, rhs(k), xw, P, st, xs, ctl_of(S), &info);
+            HJ_HIP(hipEventRecord(S.tev[1], st));
+            HJ_HIP(hipEventSynchronize(S.tev[1]));
+            if (sr == HJ_ERR_HIP || sr == HJ_ERR_INVALID_ARG) return sr;
+            if (sr != HJ_OK) {
+                ok = false;
+                break;
+            }
+            float e = 0.0f;
+            HJ_HIP(hipEventElapsedTime(&e, S.tev[0], S.tev[1]));
+            if (exact && info.cycles > 0) {
+                // an exact-regime cycle is s classical sweeps: more than
+                // (cycles - 1) s sweeps were needed
+                n_classical[(size_t)k] = std::max<int64_t>(n_classical[(size_t)k], (info.cycles - 1) * P.s + 1);
+            }
+            total += (double)e;
+            if (total >= best_t) ok = false;  // lost already
+        }
+        if (ok && total < best_t) {
+            best_t = total;
             winner = P0;
         }
     }
     g_err.clear();
-    if (!std::isfinite(best_t)) return fail(HJ_ERR_NOT_CONVERGED, "autotune_solve: no candidate reached trial_tol");
+    if (!std::isfinite(best_t))
+        return fail(HJ_ERR_NOT_CONVERGED, "autotune_solve: no candidate reached trial_tol on every right-hand side");
     *best = winner;
     best->max_cycles = tp->max_trial_cycles;
     if (best_ms) *best_ms = best_t;

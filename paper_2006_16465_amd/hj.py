@@ -75,7 +75,7 @@ class AdjointDesc(ctypes.Structure):
 class TuneParams(ctypes.Structure):
     _fields_ = [("trial_tol", ctypes.c_double), ("max_trial_cycles", ctypes.c_int64),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("nrhs", ctypes.c_int32), ("rhs_stride", ctypes.c_int64)]
 
 
 class Problem(ctypes.Structure):
@@ -444,24 +444,35 @@ def autotune_solve(f, x0=None, h=None, *, hx=None, hy=None, trial_tol=1e-6, max_
                    tile=None):
     """Cycle shape that solves this 2D problem (f, from x0, default 0) to
     trial_tol fastest, inexact overlaps included (hj_autotune_solve).
-    tile=(tx, ty) restricts the candidates to that tile.  Returns
-    (tile, s, overlap, ms of the winning trial)."""
+    f may be (nrhs, ny, nx), contiguous: several right-hand sides, scored by
+    the sum of their trial times (every one must reach trial_tol); x0 is
+    (ny, nx) and shared.  tile=(tx, ty) restricts the candidates to that
+    tile.  Returns (tile, s, overlap, ms of the winning trials)."""
     import torch
     hx = hx if hx is not None else h
     hy = hy if hy is not None else hx
-    x0 = torch.zeros_like(f) if x0 is None else x0
-    _check_pair(f, x0)
-    ld = _ld(f)
+    nrhs = 0
+    if f.dim() == 3:
+        if not f.is_contiguous():
+            raise ValueError("a stack of right-hand sides must be contiguous")
+        nrhs = f.shape[0]
+        f2 = f[0]
+    else:
+        f2 = f
+    x0 = torch.zeros_like(f2) if x0 is None else x0
+    _check_pair(f2, x0)
+    ld = _ld(f2)
     if _ld(x0) != ld:
         raise ValueError("f and x0 must share the row stride")
-    ny, nx = f.shape
+    ny, nx = f2.shape
     tp = TuneParams()
     tp.trial_tol, tp.max_trial_cycles, tp.flags = trial_tol, max_trial_cycles, 0
     tp.tile_x, tp.tile_y = tile if tile is not None else (0, 0)
+    tp.nrhs, tp.rhs_stride = nrhs, (f.stride(0) if nrhs else 0)
     p = Params()
     ms = ctypes.c_double()
     with _device(f):
-        st = load().hj_autotune_solve(nx, ny, ld, float(hx), float(hy), _dtype_code(f), f.data_ptr(),
+        st = load().hj_autotune_solve(nx, ny, ld, float(hx), float(hy), _dtype_code(f2), f.data_ptr(),
                                       x0.data_ptr(), ctypes.byref(tp), _stream(f), ctypes.byref(p), ctypes.byref(ms))
     if st != HJ_OK:
         raise HJError(st, last_error())

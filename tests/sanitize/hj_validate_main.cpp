@@ -146,6 +146,32 @@ int main()
     EXPECT(hj_solve_2d(8, 8, 8, 0.1, 0.1, (hj_dtype)-1, FAKE, FAKE, &p, nullptr, &info), HJ_ERR_INVALID_ARG);
     EXPECT(hj_residual(2, 8, 8, 8, 0.1, 0.1, (hj_dtype)123456, FAKE, FAKE, nullptr, &nrm, nullptr),
            HJ_ERR_INVALID_ARG);
+    // right-hand-side tuner
+    {
+        hj_tune_params t;
+        std::memset(&t, 0, sizeof t);
+        t.trial_tol = 1e-4;
+        t.max_trial_cycles = 100;
+        hj_params best;
+        double ms = 0.0;
+        auto tune = [&](const hj_tune_params *tp, int64_t ld) {
+            return hj_autotune_solve(64, 64, ld, 0.01, 0.01, HJ_F64, FAKE, FAKE, tp, nullptr, &best, &ms);
+        };
+        EXPECT(tune(nullptr, 64), HJ_ERR_INVALID_ARG);
+        hj_tune_params u = t;
+        u.trial_tol = 0.0;
+        EXPECT(tune(&u, 64), HJ_ERR_INVALID_ARG);
+        u = t;
+        u.nrhs = -3;
+        EXPECT(tune(&u, 64), HJ_ERR_INVALID_ARG);
+        u = t;
+        u.nrhs = 2;
+        u.rhs_stride = 64 * 64 - 1;
+        EXPECT(tune(&u, 64), HJ_ERR_INVALID_ARG);
+        u.rhs_stride = (int64_t)1 << 62;  // ny * ld would overflow int64
+        EXPECT(tune(&u, (int64_t)1 << 60), HJ_ERR_INVALID_ARG);
+    }
+
     std::printf("libhj validation sanitizer run: %d failures\n", failures);
     return failures ? 1 : 0;
 }

@@ -294,5 +294,12 @@ def test_autotune_solve_rejects_invalid_arguments():
     assert call(tp(tile_x=48, tile_y=32)) == hj.HJ_ERR_UNSUPPORTED
     assert call(tp(), ld=32) == hj.HJ_ERR_INVALID_ARG
     assert call(tp(), x0=None) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(nrhs=-1)) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(nrhs=1025, rhs_stride=64 * 64)) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(nrhs=2, rhs_stride=64 * 64 - 1)) == hj.HJ_ERR_INVALID_ARG
+    assert call(tp(nrhs=2, rhs_stride=-64)) == hj.HJ_ERR_INVALID_ARG
+    # ny * ld overflows int64 here: the check must not wrap
+    assert call(tp(nrhs=3, rhs_stride=1 << 62), ld=1 << 60) == hj.HJ_ERR_INVALID_ARG
     assert hj.last_error()
+    assert ctypes.sizeof(hj.TuneParams) == 40
 
