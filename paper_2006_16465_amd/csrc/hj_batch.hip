@@ -98,7 +98,8 @@ __device__ double ref_blocks(const BProb &P, const BState &S, int64_t item, int6
 enum : int { BM_F64 = 0, BM_F32 = 1, BM_REF = 2 };
 
 template <int M, int C, int R, int W, bool ISO>
-__global__ __launch_bounds__(64 * W) void k_batch_cycle2d(const BProb *__restrict__ probs,
+__global__ __launch_bounds__(64 * W, (min_waves_2d<std::conditional_t<M == BM_F32, float, double>, C, R>()))
+void k_batch_cycle2d(const BProb *__restrict__ probs,
                                                           const int32_t *__restrict__ owner,
                                                           int64_t nitems, const BState *__restrict__ state,
                                                           double *part, int s)

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kNT) void k_cycle2d(Geom2 g, const T *__restrict__ 
 // full tile (tile body in hj_tiles.h), fused residual of the incoming iterate.
 // ============================================================================
 template <typename T, int C, int R, int W, bool RES, bool ISO>
-__global__ __launch_bounds__(64 * W) void k_cycle2d_reg(Geom2 g, const T *__restrict__ f,
+__global__ __launch_bounds__(64 * W, (min_waves_2d<T, C, R>())) void k_cycle2d_reg(Geom2 g, const T *__restrict__ f,
                                                         const T *__restrict__ xin,
                                                         T *__restrict__ xout, int nsub, Red red,
                                                         double tol)

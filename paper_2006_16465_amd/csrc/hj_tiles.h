@@ -56,6 +56,20 @@ __device__ __forceinline__ double res1(double f, double x, double w, double e, d
 
 constexpr int kNT = 256;  // threads per workgroup of every kernel here
 
+// Minimum wavefronts per SIMD the 2D register-tile kernels ask the compiler
+// for (the second __launch_bounds__ argument).  FP64 tiles of 4 x 4 points a
+// lane (64x64, 64x128) hold 124 VGPRs with a rolled sweep loop and 132 with
+// the unrolled one: capping them at 128 (occupancy 4) spills a few values
+// outside the loop and beats occupancy 3 by far (4096^2, s = 16: 147-149
+// against 153-158 us per launch for the rolled loop at occupancy 4; 202-222
+// us at occupancy 3).  Other shapes need more registers than 4 waves allow
+// and are left to the compiler.
+template <typename T, int C, int R>
+constexpr int min_waves_2d()
+{
+    return (sizeof(T) == 8 && C == 4 && R == 4) ? 4 : 1;
+}
+
 // ============================================================================
 // 2D hierarchical cycle, register-resident.  A workgroup of W wavefronts takes
 // one full tile of TX = 16*C columns by TY = 4*R*W rows.  Thread t belongs to
@@ -377,11 +391,23 @@ __device__ __forceinline__ double reg_tile_2d(const Geom2 &g, int tile, const T 
         }
     };
 
-    // step 2: nsub sub-iterations with the halo frozen
+    // step 2: nsub sub-iterations with the halo frozen.  Two per loop trip:
+    // each exchange's LDS buffer is then a constant, and the two sweeps
+    // trade the rows' registers between them, so the loop carries no address
+    // arithmetic and no register moves (80 VALU instructions per sweep and
+    // wavefront against 104 at 4 x 4 points a lane); it takes a few more
+    // VGPRs, which the kernels cap (min_waves_2d) to keep occupancy 4.
     exchange.template operator()<0>(0);
     sweep(std::true_type{});
-    for (int it = 1; it < nsub; ++it) {
-        exchange.template operator()<0>(it & 1);
+    int it = 1;
+    for (; it + 1 < nsub; it += 2) {
+        exchange.template operator()<0>(1);
+        sweep(std::false_type{});
+        exchange.template operator()<0>(0);
+        sweep(std::false_type{});
+    }
+    if (it < nsub) {
+        exchange.template operator()<0>(1);
         sweep(std::false_type{});
     }
 
