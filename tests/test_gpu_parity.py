@@ -140,13 +140,16 @@ def test_fp32_register_kernel_equals_fp32_lds_kernel(tile):
 @pytest.mark.parametrize("overlap", [(0, 0), (14, 14), (30, 6)])
 def test_multiwave_register_kernel_matches_oracle(orc, tile, overlap):
     """Tiles held by several wavefronts (or 128 columns wide): ragged grids of a
-    few tiles per axis, with and without overlap, FP64 bit for bit."""
+    few tiles per axis, with and without overlap, FP64 bit for bit.  The
+    sub-iteration counts cover the sweep loop's two-sweeps-per-trip form:
+    s = 1 (no loop), 2 (the single leftover sweep only), 3 and 5 (whole
+    trips only), 8 (trips and a leftover)."""
     ny, nx = 300, 270
     ov = (min(overlap[0], tile[0] - 2), min(overlap[1], tile[1] - 2))
     f = W.rhs_random((ny, nx), tile[0] * 7 + tile[1] + ov[0])
     x0 = W.rhs_random((ny, nx), 11 + ov[1])
     h = 1.0 / 301
-    for s, nc in ((1, 2), (3, 3), (8, 2)):
+    for s, nc in ((1, 2), (2, 2), (3, 3), (5, 2), (8, 2)):
         say(f"multiwave tile={tile} ov={ov} s={s} nc={nc}")
         got, _ = gpu_cycles_2d(f, x0, h, tile, s, nc, ov)
         assert np.array_equal(got, orc.hier_2d(f, x0, h, h, tile, s, nc, ov))
