@@ -262,3 +262,19 @@ def test_paper_1d_experiment_shape_matches_oracle(orc, tile, s, ov, classical):
         assert i.status == hj.HJ_OK and i.cycles == co
         assert np.array_equal(host(X), xo)
         assert abs(i.rel_residual - relo) <= 1e-9 * relo
+
+
+@pytest.mark.parametrize("s,ov", [(2, 2), (7, 12)])
+def test_batch_register_tiles_at_other_sweep_counts(orc, s, ov):
+    """The 64 x 64 register tile runs two sub-iterations per loop trip: s = 2
+    takes only the leftover sweep, s = 7 only whole trips; both must give the
+    oracle's iterates for every 2D problem of a batch (fixed cycles)."""
+    probs = [pr for pr in make_batch(4) if pr[0] == "2d"]
+    xs = [torch.zeros_like(dev(f)) for _, f, _, _ in probs]
+    table = [(dev(f), X, hx, hy) for (_, f, hx, hy), X in zip(probs, xs)]
+    infos = hj.solve_batched(table, tile=(64, 64), s=s, overlap=(ov, ov), rel_tol=0.0, max_cycles=5,
+                             graph_cycles=3)
+    for i, ((_, f, hx, hy), X) in enumerate(zip(probs, xs)):
+        assert infos[i].cycles == 5
+        want = orc.hier_2d(f, np.zeros_like(f), hx, hy, (64, 64), s, 5, (ov, ov))
+        assert np.array_equal(host(X), want), f"problem {i}"
