@@ -59,11 +59,11 @@ constexpr int kNT = 256;  // threads per workgroup of every kernel here
 // Minimum wavefronts per SIMD the 2D register-tile kernels ask the compiler
 // for (the second __launch_bounds__ argument).  FP64 tiles of 4 x 4 points a
 // lane (64x64, 64x128) hold 124 VGPRs with a rolled sweep loop and 132 with
-// the unrolled one: capping them at 128 (occupancy 4) spills a few values
-// outside the loop and beats occupancy 3 by far (4096^2, s = 16: 147-149
-// against 153-158 us per launch for the rolled loop at occupancy 4; 202-222
-// us at occupancy 3).  Other shapes need more registers than 4 waves allow
-// and are left to the compiler.
+// the unrolled one: capped at 128 (occupancy 4) the compiler spills one
+// double outside the loop, and the launch beats the rolled loop (4096^2,
+// s = 16: 147-150 against 153-158 us); left at 132 VGPRs (occupancy 3) an
+// s = 12 launch took over 200 us against 135.  Other shapes need more
+// registers than 4 waves allow and are left to the compiler.
 template <typename T, int C, int R>
 constexpr int min_waves_2d()
 {
