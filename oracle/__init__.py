@@ -14,7 +14,9 @@ source; briefly:
 * ``hier_*``     hierarchical cycles (Sec. 3.3 three-step cycle, Sec. 4.1 in
   2D, overlapping subdomains Sec. 3.5 / Sec. 4.3);
 * ``residual_*`` r = f - A x and its 2-norm (stopping rule of Sec. 3.4);
-* ``solve_*``    iterate until ||r_n|| <= tol ||r_0||, checking every cycle.
+* ``solve_*``    iterate until ||r_n|| <= tol ||r_0||, checking every cycle;
+* ``*_f32``      the same sweeps and cycles in single precision, for checking
+  an FP32 instantiation (float32 in and out).
 """
 import ctypes
 import os
@@ -29,6 +31,7 @@ _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
 _f64 = ctypes.c_double
 _pd = ctypes.POINTER(ctypes.c_double)
+_pf = ctypes.POINTER(ctypes.c_float)
 _pi64 = ctypes.POINTER(ctypes.c_int64)
 
 HIERARCHICAL = 0
@@ -51,6 +54,10 @@ def _load():
         "orc_jacobi_2d": (None, [_i64, _i64, _f64, _f64, _pd, _pd, _i64]),
         "orc_hier_1d": (None, [_i64, _f64, _pd, _pd, _i64, _i64, _i64, _i64]),
         "orc_hier_2d": (None, [_i64, _i64, _f64, _f64, _pd, _pd, _i64, _i64, _i64, _i64, _i64, _i64]),
+        "orc_jacobi_1d_f32": (None, [_i64, _f64, _pf, _pf, _i64]),
+        "orc_jacobi_2d_f32": (None, [_i64, _i64, _f64, _f64, _pf, _pf, _i64]),
+        "orc_hier_1d_f32": (None, [_i64, _f64, _pf, _pf, _i64, _i64, _i64, _i64]),
+        "orc_hier_2d_f32": (None, [_i64, _i64, _f64, _f64, _pf, _pf, _i64, _i64, _i64, _i64, _i64, _i64]),
         "orc_residual_1d": (_f64, [_i64, _f64, _pd, _pd, _pd]),
         "orc_residual_2d": (_f64, [_i64, _i64, _f64, _f64, _pd, _pd, _pd]),
         "orc_solve_1d": (_i64, [_i64, _f64, _pd, _pd, _i32, _i64, _i64, _i64, _f64, _i64, _pd, _pd]),
@@ -80,6 +87,17 @@ def _arr(a, shape=None):
 
 def _p(a):
     return a.ctypes.data_as(_pd)
+
+
+def _arr32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _p32(a):
+    return a.ctypes.data_as(_pf)
 
 
 def num_threads() -> int:
@@ -158,6 +176,45 @@ def hier_2d(f, x0, hx, hy, tile, s, ncycles, overlap=(0, 0)):
     _check_tile(tx, ox, s)
     _check_tile(ty, oy, s)
     _load().orc_hier_2d(nx, ny, hx, hy, _p(f), _p(x), tx, ty, ox, oy, int(s), int(ncycles))
+    return x
+
+
+# ---------------------------------------------------------------- FP32
+# The same sweeps and cycles in single precision (readings in the C source):
+# inputs are rounded to float32 first; results are float32 arrays.
+
+def jacobi_1d_f32(f, x0, h, nsweeps):
+    f = _arr32(f)
+    x = _arr32(x0, f.shape).copy()
+    _load().orc_jacobi_1d_f32(f.size, h, _p32(f), _p32(x), int(nsweeps))
+    return x
+
+
+def hier_1d_f32(f, x0, h, tile, s, ncycles, overlap=0):
+    f = _arr32(f)
+    x = _arr32(x0, f.shape).copy()
+    _check_tile(tile, overlap, s)
+    _load().orc_hier_1d_f32(f.size, h, _p32(f), _p32(x), int(tile), int(overlap), int(s), int(ncycles))
+    return x
+
+
+def jacobi_2d_f32(f, x0, hx, hy, nsweeps):
+    f = _arr32(f)
+    ny, nx = f.shape
+    x = _arr32(x0, f.shape).copy()
+    _load().orc_jacobi_2d_f32(nx, ny, hx, hy, _p32(f), _p32(x), int(nsweeps))
+    return x
+
+
+def hier_2d_f32(f, x0, hx, hy, tile, s, ncycles, overlap=(0, 0)):
+    f = _arr32(f)
+    ny, nx = f.shape
+    x = _arr32(x0, f.shape).copy()
+    tx, ty = tile
+    ox, oy = overlap
+    _check_tile(tx, ox, s)
+    _check_tile(ty, oy, s)
+    _load().orc_hier_2d_f32(nx, ny, hx, hy, _p32(f), _p32(x), tx, ty, ox, oy, int(s), int(ncycles))
     return x
 
 

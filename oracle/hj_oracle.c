@@ -44,6 +44,9 @@
  *   - residual r = f - A x over interior points; norms are 2-norms summed with
  *     Neumaier compensation; convergence when ||r_n|| <= tol * ||r_0||.
  *
+ * An FP32 section (orc_*_f32) carries the same sweeps and cycles out in single
+ * precision for checking an FP32 instantiation; its readings are stated there.
+ *
  * Layout: 1D arrays hold the n interior points; 2D arrays are row-major
  * [ny][nx] (row = y index, column = x index), interior points only.  Points
  * outside the domain read as the Dirichlet value 0.
@@ -311,6 +314,180 @@ void orc_hier_2d(int64_t nx, int64_t ny, double hx, double hy, const double *f, 
         double *tmp = cur; cur = nxt; nxt = tmp;
     }
     if (cur != x) memcpy(x, cur, sizeof(double) * (size_t)(nx * ny));
+    free(y);
+}
+
+/* ------------------------------------------------------------------ */
+/* FP32 sweeps and cycles                                               */
+/* ------------------------------------------------------------------ */
+/*
+ * The paper computes in double precision (Sec. 3.4, Sec. 4.2).  These are
+ * the same classical sweeps and hierarchical cycles carried out in single
+ * precision, for checking an FP32 instantiation bit for bit.  Readings:
+ *   - the coefficients are formed in FP64 from the spacings, exactly as
+ *     above (h*h, 1/hx^2, 1/hy^2, 1/(2 wx + 2 wy)), then rounded once to FP32;
+ *   - every operation of an update is an FP32 operation, in the association
+ *     of the FP64 updates: h^2 f is the FP32 product of the rounded h^2 and f.
+ * Kept apart from the FP64 code above so that nothing there changes.
+ */
+
+static float upd1f(float bh, float w, float e)
+{
+    return (bh + (w + e)) * 0.5f;
+}
+
+typedef struct {
+    int iso;
+    float hh, wx, wy, dinv;
+} coef2f;
+
+static coef2f make_coef2f(double hx, double hy)
+{
+    const double wx = 1.0 / (hx * hx), wy = 1.0 / (hy * hy);
+    coef2f c;
+    c.iso = (hx == hy);
+    c.hh = (float)(hx * hx);
+    c.wx = (float)wx;
+    c.wy = (float)wy;
+    c.dinv = (float)(1.0 / (2.0 * wx + 2.0 * wy));
+    return c;
+}
+
+static float upd2f(const coef2f *c, float f, float w, float e, float s, float n)
+{
+    if (c->iso) {
+        float bh = c->hh * f;
+        return (bh + ((w + e) + (s + n))) * 0.25f;
+    }
+    return (f + (c->wx * (w + e) + c->wy * (s + n))) * c->dinv;
+}
+
+void orc_jacobi_1d_f32(int64_t n, double h, const float *f, float *x, int64_t nsweeps)
+{
+    const float hh = (float)(h * h);
+    float *y = (float *)malloc(sizeof(float) * (size_t)n);
+    float *cur = x, *nxt = y;
+    for (int64_t k = 0; k < nsweeps; ++k) {
+        for (int64_t i = 0; i < n; ++i) {
+            float w = i > 0 ? cur[i - 1] : 0.0f;
+            float e = i < n - 1 ? cur[i + 1] : 0.0f;
+            nxt[i] = upd1f(hh * f[i], w, e);
+        }
+        float *t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != x) memcpy(x, cur, sizeof(float) * (size_t)n);
+    free(y);
+}
+
+void orc_jacobi_2d_f32(int64_t nx, int64_t ny, double hx, double hy, const float *f, float *x,
+                       int64_t nsweeps)
+{
+    const coef2f c = make_coef2f(hx, hy);
+    float *y = (float *)malloc(sizeof(float) * (size_t)(nx * ny));
+    float *cur = x, *nxt = y;
+    for (int64_t k = 0; k < nsweeps; ++k) {
+        #pragma omp parallel for schedule(static) if (nx * ny >= PAR_MIN_POINTS)
+        for (int64_t r = 0; r < ny; ++r) {
+            for (int64_t q = 0; q < nx; ++q) {
+                float w = q > 0 ? cur[r * nx + q - 1] : 0.0f;
+                float e = q < nx - 1 ? cur[r * nx + q + 1] : 0.0f;
+                float so = r > 0 ? cur[(r - 1) * nx + q] : 0.0f;
+                float no = r < ny - 1 ? cur[(r + 1) * nx + q] : 0.0f;
+                nxt[r * nx + q] = upd2f(&c, f[r * nx + q], w, e, so, no);
+            }
+        }
+        float *t = cur; cur = nxt; nxt = t;
+    }
+    if (cur != x) memcpy(x, cur, sizeof(float) * (size_t)(nx * ny));
+    free(y);
+}
+
+/* the three steps of Sec. 3.3 for one tile of a 1D cycle, in FP32 */
+void orc_hier_1d_f32(int64_t n, double h, const float *f, float *x, int64_t t, int64_t o,
+                     int64_t s, int64_t ncycles)
+{
+    const float hh = (float)(h * h);
+    const int64_t nt = orc_axis_ntiles(n, t, o), ext = axis_extent(n, t);
+    float *y = (float *)malloc(sizeof(float) * (size_t)n);
+    float *L0 = (float *)malloc(sizeof(float) * (size_t)(ext + 2));
+    float *L1 = (float *)malloc(sizeof(float) * (size_t)(ext + 2));
+    float *cur = x, *nxt = y;
+    for (int64_t cyc = 0; cyc < ncycles; ++cyc) {
+        for (int64_t ti = 0; ti < nt; ++ti) {
+            const int64_t x0 = orc_axis_start(n, t, o, ti);
+            float *L[2] = {L0, L1};
+            for (int64_t j = -1; j <= ext; ++j) {
+                const int64_t g = x0 + j;
+                const float v = (g >= 0 && g < n) ? cur[g] : 0.0f;
+                L[0][j + 1] = v;
+                L[1][j + 1] = v;
+            }
+            for (int64_t k = 0; k < s; ++k) {
+                const float *src = L[k % 2];
+                float *dst = L[(k + 1) % 2];
+                for (int64_t j = 0; j < ext; ++j) dst[j + 1] = upd1f(hh * f[x0 + j], src[j], src[j + 2]);
+            }
+            const float *res = L[s % 2];
+            int64_t lo, hi;
+            orc_axis_owned(n, t, o, ti, &lo, &hi);
+            for (int64_t g = lo; g < hi; ++g) nxt[g] = res[g - x0 + 1];
+        }
+        float *tmp = cur; cur = nxt; nxt = tmp;
+    }
+    if (cur != x) memcpy(x, cur, sizeof(float) * (size_t)n);
+    free(L0);
+    free(L1);
+    free(y);
+}
+
+/* the three steps of Sec. 4.1 for every tile of a 2D cycle, in FP32 */
+void orc_hier_2d_f32(int64_t nx, int64_t ny, double hx, double hy, const float *f, float *x,
+                     int64_t tx, int64_t ty, int64_t ox, int64_t oy, int64_t s, int64_t ncycles)
+{
+    const coef2f c = make_coef2f(hx, hy);
+    const int64_t ntx = orc_axis_ntiles(nx, tx, ox), nty = orc_axis_ntiles(ny, ty, oy);
+    const int64_t ex = axis_extent(nx, tx), ey = axis_extent(ny, ty), p = ex + 2;
+    float *y = (float *)malloc(sizeof(float) * (size_t)(nx * ny));
+    float *cur = x, *nxt = y;
+    for (int64_t cyc = 0; cyc < ncycles; ++cyc) {
+        #pragma omp parallel for schedule(static) if (ntx * nty * ex * ey * s >= PAR_MIN_POINTS)
+        for (int64_t tid = 0; tid < ntx * nty; ++tid) {
+            const int64_t bi = tid / ntx, bj = tid % ntx;
+            const int64_t r0 = orc_axis_start(ny, ty, oy, bi), c0 = orc_axis_start(nx, tx, ox, bj);
+            float *L[2];
+            L[0] = (float *)malloc(sizeof(float) * (size_t)(p * (ey + 2)));
+            L[1] = (float *)malloc(sizeof(float) * (size_t)(p * (ey + 2)));
+            for (int64_t r = -1; r <= ey; ++r) {
+                for (int64_t q = -1; q <= ex; ++q) {
+                    const int64_t gr = r0 + r, gq = c0 + q;
+                    const float v = (gr >= 0 && gr < ny && gq >= 0 && gq < nx) ? cur[gr * nx + gq] : 0.0f;
+                    L[0][(r + 1) * p + (q + 1)] = v;
+                    L[1][(r + 1) * p + (q + 1)] = v;
+                }
+            }
+            for (int64_t k = 0; k < s; ++k) {
+                const float *src = L[k % 2];
+                float *dst = L[(k + 1) % 2];
+                for (int64_t r = 0; r < ey; ++r) {
+                    for (int64_t q = 0; q < ex; ++q) {
+                        const int64_t a = (r + 1) * p + (q + 1);
+                        dst[a] = upd2f(&c, f[(r0 + r) * nx + (c0 + q)], src[a - 1], src[a + 1], src[a - p],
+                                       src[a + p]);
+                    }
+                }
+            }
+            const float *res = L[s % 2];
+            int64_t rlo, rhi, qlo, qhi;
+            orc_axis_owned(ny, ty, oy, bi, &rlo, &rhi);
+            orc_axis_owned(nx, tx, ox, bj, &qlo, &qhi);
+            for (int64_t gr = rlo; gr < rhi; ++gr)
+                for (int64_t gq = qlo; gq < qhi; ++gq) nxt[gr * nx + gq] = res[(gr - r0 + 1) * p + (gq - c0 + 1)];
+            free(L[0]);
+            free(L[1]);
+        }
+        float *tmp = cur; cur = nxt; nxt = tmp;
+    }
+    if (cur != x) memcpy(x, cur, sizeof(float) * (size_t)(nx * ny));
     free(y);
 }
 
