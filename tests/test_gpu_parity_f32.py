@@ -98,3 +98,28 @@ def test_fp32_batch_equals_fp32_oracle(orc):
     for i, ((_, X, _, _), want) in enumerate(zip(table, wants)):
         assert infos[i].cycles == 7
         assert np.array_equal(host32(X), want), f"problem {i}"
+
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_refined_solve_is_oracle_fp64_cycles_plus_fp32_correction(orc, seed):
+    """One refinement step rebuilt from the oracle, bit for bit: FP64 cycles
+    up to the hand-over (fp64_cycles of them), r = f - A x in FP64 rounded to
+    FP32, FP32 cycles on A e = r from e = 0 (inner_cycles of them), then
+    x + e in FP64.  256^2, 64 x 32 tiles, s = 8, overlap 14, to 1e-10 with
+    the hand-over allowed from the first cycle on."""
+    n = 256
+    h = 1.0 / (n + 1)
+    kw = dict(tile=(64, 32), s=8, overlap=(14, 14))
+    f = W.rhs_2d_modes(n, n, 8, 0.0, seed)
+    X = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    info = hj.solve_2d_refined(torch.as_tensor(f).cuda(), X, h, rel_tol=1e-10, inner_tol=1e-6, switch_min_cycles=1,
+                               **kw)
+    say(f"refined seed {seed}: outer {info.outer}, fp64 {info.fp64_cycles}, fp32 {info.inner_cycles}")
+    assert info.outer == 1 and info.inner_cycles > 0
+    x1 = orc.hier_2d(f, np.zeros_like(f), h, h, kw["tile"], kw["s"], info.fp64_cycles, kw["overlap"])
+    r, _ = orc.residual_2d(f, x1, h, h)
+    e = orc.hier_2d_f32(r.astype(np.float32), np.zeros((n, n)), h, h, kw["tile"], kw["s"], info.inner_cycles,
+                        kw["overlap"])
+    want = x1 + e.astype(np.float64)
+    torch.cuda.synchronize()
+    assert np.array_equal(X.cpu().numpy(), want)
