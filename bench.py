@@ -566,15 +566,13 @@ def mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream):
     both to args.mixed_tol on the same right-hand sides (per-seed medians of
     5 interleaved timed calls each).  The FP64 path equals
     the CPU oracle bit for bit (GPU tests); the refined solution's distance to
-    it is reported per seed."""
+    it is reported per seed.  Two shapes: the exact-regime shape of the
+    headline rows (top-level keys), and the workload's own 64x64 tiles with s
+    and overlap from hj_autotune_solve restricted to that tile, tuned on
+    right-hand sides the timed seeds do not include (config3_64x64)."""
+    from paper_2006_16465_amd import workloads as W
+
     log(f"mixed precision: FP64 vs FP32 + FP64 refinement to {args.mixed_tol:g}")
-    exact = min(ov) >= 2 * s - 2
-    out = {"tol": args.mixed_tol, "inner_tol": args.inner_tol,
-           "switch_tol": (1e5 if exact else 1e4) * args.mixed_tol,
-           "switch_rule": "library default: 1e5 tol in the exact regime (overlap >= 2s - 2), else 1e4 tol",
-           "fp64_ms": {}, "refined_ms": {},
-           "fp64_cycles": {}, "refined_fp64_cycles": {}, "refined_inner_cycles": {}, "refined_outer": {},
-           "rel_diff_refined_vs_fp64": {}}
     x64 = torch.zeros_like(fs[0])
 
     def timed_call(fn):
@@ -586,32 +584,59 @@ def mixed_rows(args, torch, hj, fs, xs, h, tile, s, ov, stream):
         e1.synchronize()
         return e0.elapsed_time(e1), r
 
-    for sd, f, x in zip(args.seeds, fs, xs):
-        # one untimed call of each (scratch warm-up), then 5 interleaved timed
-        # calls of each; per-seed medians
-        t64s, tmxs = [], []
-        for rep in range(6):
-            x64.zero_()
-            t64, i64 = timed_call(lambda: hj.solve_2d(f, x64, h, tile=tile, s=s, overlap=ov,
-                                                      rel_tol=args.mixed_tol))
-            x.zero_()
-            tmx, imx = timed_call(lambda: hj.solve_2d_refined(
-                f, x, h, tile=tile, s=s, overlap=ov, rel_tol=args.mixed_tol, inner_tol=args.inner_tol))
-            if rep > 0:
-                t64s.append(t64)
-                tmxs.append(tmx)
-        k = str(sd)
-        out["fp64_ms"][k] = round(float(np.median(t64s)), 3)
-        out["refined_ms"][k] = round(float(np.median(tmxs)), 3)
-        out["fp64_cycles"][k] = i64.cycles
-        out["refined_fp64_cycles"][k] = imx.fp64_cycles
-        out["refined_inner_cycles"][k] = imx.inner_cycles
-        out["refined_outer"][k] = imx.outer
-        out["rel_diff_refined_vs_fp64"][k] = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
-    out["fp64_ms_per_problem"] = round(sum(out["fp64_ms"].values()) / len(fs), 3)
-    out["refined_ms_per_problem"] = round(sum(out["refined_ms"].values()) / len(fs), 3)
-    out["speedup_refined_vs_fp64"] = round(out["fp64_ms_per_problem"] / out["refined_ms_per_problem"], 3)
-    return out
+    def rows(tile, s, ov):
+        exact = min(ov) >= 2 * s - 2
+        out = {"tile": list(tile), "s": s, "overlap": list(ov), "tol": args.mixed_tol,
+               "inner_tol": args.inner_tol,
+               "switch_tol": (1e5 if exact else 1e4) * args.mixed_tol,
+               "switch_rule": "library default: 1e5 tol in the exact regime (overlap >= 2s - 2), else 1e4 tol",
+               "fp64_ms": {}, "refined_ms": {},
+               "fp64_cycles": {}, "refined_fp64_cycles": {}, "refined_inner_cycles": {}, "refined_outer": {},
+               "rel_diff_refined_vs_fp64": {}}
+        for sd, f, x in zip(args.seeds, fs, xs):
+            # one untimed call of each (scratch warm-up), then 5 interleaved timed
+            # calls of each; per-seed medians
+            t64s, tmxs = [], []
+            for rep in range(6):
+                x64.zero_()
+                t64, i64 = timed_call(lambda: hj.solve_2d(f, x64, h, tile=tile, s=s, overlap=ov,
+                                                          rel_tol=args.mixed_tol))
+                x.zero_()
+                tmx, imx = timed_call(lambda: hj.solve_2d_refined(
+                    f, x, h, tile=tile, s=s, overlap=ov, rel_tol=args.mixed_tol, inner_tol=args.inner_tol))
+                if rep > 0:
+                    t64s.append(t64)
+                    tmxs.append(tmx)
+            k = str(sd)
+            out["fp64_ms"][k] = round(float(np.median(t64s)), 3)
+            out["refined_ms"][k] = round(float(np.median(tmxs)), 3)
+            out["fp64_cycles"][k] = i64.cycles
+            out["refined_fp64_cycles"][k] = imx.fp64_cycles
+            out["refined_inner_cycles"][k] = imx.inner_cycles
+            out["refined_outer"][k] = imx.outer
+            out["rel_diff_refined_vs_fp64"][k] = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        out["fp64_ms_per_problem"] = round(sum(out["fp64_ms"].values()) / len(fs), 3)
+        out["refined_ms_per_problem"] = round(sum(out["refined_ms"].values()) / len(fs), 3)
+        out["speedup_refined_vs_fp64"] = round(out["fp64_ms_per_problem"] / out["refined_ms_per_problem"], 3)
+        return out
+
+    res = rows(tile, s, ov)
+    n = fs[0].shape[0]
+    tune_seeds = (5, 6, 7)
+    f5 = torch.from_numpy(np.stack([W.rhs_2d_modes(n, n, 8, 0.0, sd) for sd in tune_seeds])).to(fs[0].device)
+    t0 = time.perf_counter()
+    # trial solves to the row's own tolerance: a near-exact overlap that wins
+    # at 1e-6 can stall on the way to 1e-10 (the stale halo's small weight
+    # matters more the further the residual has to fall)
+    t3, s3, ov3, _ = hj.autotune_solve(f5, None, h, trial_tol=args.mixed_tol, tile=(64, 64))
+    tune_s = time.perf_counter() - t0
+    del f5
+    log(f"mixed precision, 64x64 tiles: tuned s {s3}, overlap {ov3} ({tune_s:.1f} s)")
+    res["config3_64x64"] = rows(t3, s3, ov3)
+    res["config3_64x64"]["tuned_on"] = (f"seeds {', '.join(map(str, tune_seeds))} together: hj_autotune_solve "
+                                        f"with the tile fixed at 64x64, FP64 trial solves to {args.mixed_tol:g}")
+    res["config3_64x64"]["tuning_s"] = round(tune_s, 2)
+    return res
 
 
 def batched_rows(args, torch, hj, stream):
