@@ -174,7 +174,6 @@ def main():
     ap.add_argument("--no-replica", action="store_true",
                     help="skip the rows on the paper's own experiment shapes (b = 1, x0 = 1, 1e-4)")
     ap.add_argument("--inner-tol", type=float, default=1e-6)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample budget")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
