@@ -522,6 +522,22 @@ hj_status time_shape(int dim, int64_t nx, int64_t ny, hj_dtype dt, const hj_para
     return HJ_OK;
 }
 
+// Points a cycle's tiles load per grid point along both axes (1: no
+// redundancy).  Tuners skip shapes that load more than kMaxLoadFactor times
+// the grid: a cycle's cost grows with that factor and its sweeps with s <=
+// 32 at most, so such a shape takes at least twice as long per classical
+// sweep as the compact ones (about 0.15 of a load per sweep), while timing
+// it (tiles every two points, say) costs more than all other candidates.
+constexpr double kMaxLoadFactor = 8.0;
+
+double load_factor(int64_t nx, int64_t ny, int tx, int ty, int ox, int oy)
+{
+    auto axis = [](int64_t n, int t, int o) {
+        return (double)hj::axis_count((int)n, t, o) * (double)std::min<int64_t>(n, t) / (double)n;
+    };
+    return axis(nx, tx, ox) * (ny > 1 ? axis(ny, ty, oy) : 1.0);
+}
+
 hj_status autotune_locked(int dim, int64_t nx, int64_t ny, hj_dtype dt, int txmax, int tymax,
                           hipStream_t st, int dev, DevScratch &S, hj_params &best, double &best_us)
 {
@@ -553,6 +569,7 @@ hj_status autotune_locked(int dim, int64_t nx, int64_t ny, hj_dtype dt, int txma
         P.s = s;
         P.overlap_x = 2 * s - 2;
         P.overlap_y = dim == 2 ? 2 * s - 2 : 0;
+        if (load_factor(nx, ny, tx, dim == 2 ? ty : 1, P.overlap_x, P.overlap_y) > kMaxLoadFactor) return;
         cands.push_back(P);
     };
     if (dim == 2) {
@@ -1450,6 +1467,7 @@ hj_status hj_autotune_solve(int64_t nx, int64_t ny, int64_t ld, double hx, doubl
                 for (const int o : {2 * s - 2, 2 * s - 6, 2 * s - 10, three_halves, s + 6, s + 2, 8, 4, 2, 0}) {
                     if ((o == 2 * s - 2) != exact || o >= std::min(tx, ty) || o < 0) continue;
                     if (!exact && o >= 2 * s - 2) continue;
+                    if (load_factor(nx, ny, tx, ty, o, o) > kMaxLoadFactor) continue;
                     hj_params P = base;
                     P.tile_x = tx;
                     P.tile_y = ty;
